@@ -1,0 +1,89 @@
+/*
+ * MDF-FDLBM CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, sequential FP64 implementation of the time step of the
+ * multiple-distribution-function finite-difference lattice Boltzmann method
+ * (Chen, Chai, Zhao & Shi, "Multiple-distribution-function finite-difference
+ * lattice Boltzmann method for incompressible Navier-Stokes equation").
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no source, header, table or
+ * constant with the HIP library; both sides see only the same raw inputs
+ * (problem parameters, initial fields, grid metric arrays).
+ *
+ * Layout of every distribution array exchanged with this library:
+ *   f[(alpha*5 + j)*ny*nx + y*nx + x],  alpha in {0 (u), 1 (v)}, j in 0..4,
+ *   D2Q5 velocities c_j = c*{(0,0),(1,0),(0,1),(-1,0),(0,-1)}  (Sec. 3.1, eq. 3.1.0).
+ */
+#ifndef MDF_ORACLE_H
+#define MDF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
+
+typedef struct {
+    int32_t nx, ny;          /* nodes per axis (wall axes include both wall nodes)   */
+    double  lx, ly;          /* domain lengths                                       */
+    double  nu;              /* Newtonian viscosity, or consistency K if pl_n != 1   */
+    double  pl_n;            /* power-law index (1 = Newtonian)                      */
+    double  nu_min, nu_max;  /* clamp of the local power-law viscosity              */
+    double  cfl, c, eta, s_ratio;
+    int32_t bc_x, bc_y;      /* ORC_PERIODIC or ORC_WALL                             */
+    double  lid_u;           /* tangential velocity of the top (y = ly) wall         */
+    double  fx, fy;          /* uniform body force                                   */
+    const double* inv_dx_x;  /* nx entries: d(xi)/dx / d(xi), i.e. 1/(X'(xi_i) dxi); NULL = uniform */
+    const double* inv_dx_y;  /* ny entries, same meaning for y                        */
+    double  dx_min;          /* smallest node spacing; used for dt when metrics are given */
+} orc_params;
+
+typedef struct orc_state orc_state;
+
+/* Create a state initialised with f_hat = f^eq(u0, v0, p0) (Sec. 4, first
+ * paragraph), then the wall rule applied to it.  Returns NULL on bad input. */
+orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, const double* p0);
+void       orc_destroy(orc_state* st);
+void       orc_step(orc_state* st, int32_t nsteps);
+double     orc_dt(const orc_state* st);
+int64_t    orc_steps(const orc_state* st);
+void       orc_get_f(const orc_state* st, double* f);
+void       orc_set_f(orc_state* st, const double* f);
+/* intermediate fields of the last step: 0 f_hat^+(t), 1 f_bar^+(t), 2 f_bar(t+h), 3 f(t+h) */
+void       orc_fields(const orc_state* st, int32_t which, double* out);
+void       orc_moments(const orc_state* st, double* u, double* v, double* p);
+/* 14 planes, each ny*nx: ux uy vx vy div Sxx Sxy Syy sig_xx sig_xy sig_yy Omega_xy omega nu */
+void       orc_derived(const orc_state* st, double* out);
+/* 8 scalars: sum u, sum v, KE, enstrophy, max|u|, max|FD div u|, non-finite count, area */
+void       orc_diagnostics(const orc_state* st, double* out);
+
+/* ---- pieces exposed so that tests can pin them one by one ---- */
+/* f^eq for one node (eq. 2.2.5): out[alpha*5+j] */
+void   orc_feq(double c, double u, double v, double P, double* out);
+/* moments of any stored form: u, v, P (eq. 2.3.23 with R = 0) */
+void   orc_node_moments(double c, const double* phi, double* u, double* v, double* P);
+/* collision matrices for rates (s, s'), time step dt (5x5, row-major):
+ *   out[0]  = Lambda~                        (eq. 2.2.4 MRT matrix)
+ *   out[25] = I - Lambda                     (eq. 2.2.14)
+ *   out[50] = I - 3/4 Lambda                 (eq. 2.2.15)
+ *   out[75] = (I + h/2 Lambda~)^-1           (eq. 2.2.16, h = dt/2)
+ *   out[100]= (I + dt/2 Lambda~)^-1          (inverse of eq. 2.2.2)     */
+void   orc_collision_matrices(double s, double sp, double dt, double* out);
+/* one full collision of Step (1) at a node: fhat -> (fhat_plus, fbar_plus) */
+void   orc_collide_step1(const orc_state* st, const double* fhat, double* fhat_plus, double* fbar_plus);
+/* mixed-difference derivative (eqs. 2.2.12-2.2.13) of one plane along an
+ * axis (0 = x, 1 = y) for a velocity sign (+1 or -1) at every node where the
+ * stencil is evaluated; out is ny*nx. */
+void   orc_mixed_derivative(const orc_state* st, const double* field, int32_t axis, int32_t sign, double* out);
+/* wall rule applied in place to a 10-plane field */
+void   orc_wall_update(const orc_state* st, double* field);
+/* local power-law viscosity for a non-equilibrium strain magnitude gam_hat and offset theta */
+double orc_powerlaw_nu(const orc_state* st, double gam_hat, double theta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,196 @@
+"""ctypes front end of the CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Loaded by tests/, the smoke check and the CPU baseline of the benchmark; the
+product path never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborc.so")
+
+_dp = C.POINTER(C.c_double)
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("lx", C.c_double), ("ly", C.c_double),
+        ("nu", C.c_double),
+        ("pl_n", C.c_double), ("nu_min", C.c_double), ("nu_max", C.c_double),
+        ("cfl", C.c_double), ("c", C.c_double), ("eta", C.c_double), ("s_ratio", C.c_double),
+        ("bc_x", C.c_int32), ("bc_y", C.c_int32),
+        ("lid_u", C.c_double),
+        ("fx", C.c_double), ("fy", C.c_double),
+        ("inv_dx_x", _dp), ("inv_dx_y", _dp),
+        ("dx_min", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.POINTER(OrcParams), _dp, _dp, _dp]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_step.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_dt.restype = C.c_double
+        L.orc_dt.argtypes = [C.c_void_p]
+        L.orc_steps.restype = C.c_int64
+        L.orc_steps.argtypes = [C.c_void_p]
+        for name in ("orc_get_f", "orc_derived", "orc_diagnostics"):
+            getattr(L, name).argtypes = [C.c_void_p, _dp]
+        L.orc_set_f.argtypes = [C.c_void_p, _dp]
+        L.orc_fields.argtypes = [C.c_void_p, C.c_int32, _dp]
+        L.orc_moments.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.orc_feq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_node_moments.argtypes = [C.c_double, _dp, _dp, _dp, _dp]
+        L.orc_collision_matrices.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_collide_step1.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.orc_mixed_derivative.argtypes = [C.c_void_p, _dp, C.c_int32, C.c_int32, _dp]
+        L.orc_wall_update.argtypes = [C.c_void_p, _dp]
+        L.orc_powerlaw_nu.restype = C.c_double
+        L.orc_powerlaw_nu.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _params(prob):
+    keep = []
+    gx = None if prob.inv_dx_x is None else np.ascontiguousarray(prob.inv_dx_x, dtype=np.float64)
+    gy = None if prob.inv_dx_y is None else np.ascontiguousarray(prob.inv_dx_y, dtype=np.float64)
+    keep += [gx, gy]
+    p = OrcParams(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
+                  prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
+                  prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min)
+    return p, keep
+
+
+class Oracle:
+    """One oracle run of a problems.Problem."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        self._p, self._keep = _params(prob)
+        u0 = np.ascontiguousarray(prob.u0, dtype=np.float64)
+        v0 = np.ascontiguousarray(prob.v0, dtype=np.float64)
+        p0 = np.ascontiguousarray(prob.p0, dtype=np.float64)
+        self._h = lib().orc_create(C.byref(self._p), _ptr(u0), _ptr(v0), _ptr(p0))
+        if not self._h:
+            raise ValueError("oracle rejected the problem parameters")
+        self.nx, self.ny = prob.nx, prob.ny
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def dt(self) -> float:
+        return lib().orc_dt(self._h)
+
+    @property
+    def steps(self) -> int:
+        return lib().orc_steps(self._h)
+
+    def step(self, n: int = 1):
+        lib().orc_step(self._h, int(n))
+        return self
+
+    def f(self) -> np.ndarray:
+        out = np.empty((10, self.ny, self.nx))
+        lib().orc_get_f(self._h, _ptr(out))
+        return out
+
+    def set_f(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (10, self.ny, self.nx)
+        lib().orc_set_f(self._h, _ptr(f))
+
+    def fields(self, which: int) -> np.ndarray:
+        """Intermediate field of the last step: 0 f_hat^+, 1 f_bar^+, 2 f_bar(t+h), 3 f(t+h)."""
+        out = np.empty((10, self.ny, self.nx))
+        lib().orc_fields(self._h, int(which), _ptr(out))
+        return out
+
+    def moments(self):
+        u = np.empty((self.ny, self.nx))
+        v = np.empty_like(u)
+        p = np.empty_like(u)
+        lib().orc_moments(self._h, _ptr(u), _ptr(v), _ptr(p))
+        return u, v, p
+
+    def derived(self) -> np.ndarray:
+        out = np.empty((14, self.ny, self.nx))
+        lib().orc_derived(self._h, _ptr(out))
+        return out
+
+    def diagnostics(self) -> np.ndarray:
+        out = np.empty(8)
+        lib().orc_diagnostics(self._h, _ptr(out))
+        return out
+
+    def mixed_derivative(self, plane: np.ndarray, axis: int, sign: int) -> np.ndarray:
+        plane = np.ascontiguousarray(plane, dtype=np.float64)
+        out = np.empty_like(plane)
+        lib().orc_mixed_derivative(self._h, _ptr(plane), axis, sign, _ptr(out))
+        return out
+
+    def wall_update(self, field: np.ndarray) -> np.ndarray:
+        field = np.array(field, dtype=np.float64, order="C", copy=True)
+        lib().orc_wall_update(self._h, _ptr(field))
+        return field
+
+    def collide_step1(self, fhat_node: np.ndarray):
+        fh = np.ascontiguousarray(fhat_node, dtype=np.float64)
+        a = np.empty(10)
+        b = np.empty(10)
+        lib().orc_collide_step1(self._h, _ptr(fh), _ptr(a), _ptr(b))
+        return a, b
+
+    def powerlaw_nu(self, gam_hat: float, theta: float) -> float:
+        return lib().orc_powerlaw_nu(self._h, gam_hat, theta)
+
+
+def feq(c: float, u: float, v: float, P: float) -> np.ndarray:
+    out = np.empty(10)
+    lib().orc_feq(c, u, v, P, _ptr(out))
+    return out
+
+
+def node_moments(c: float, phi: np.ndarray):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    u, v, P = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_node_moments(c, _ptr(phi), C.byref(u), C.byref(v), C.byref(P))
+    return u.value, v.value, P.value
+
+
+def collision_matrices(s: float, sp: float, dt: float):
+    out = np.empty(125)
+    lib().orc_collision_matrices(s, sp, dt, _ptr(out))
+    m = out.reshape(5, 5, 5)
+    return {"Lt": m[0], "ImL": m[1], "Ib": m[2], "Cinv": m[3], "Ainv": m[4]}

@@ -1,0 +1,248 @@
+"""Seeded synthetic problem definitions: grids, parameters and initial fields.
+
+This module describes inputs only -- the flow problems of Sec. 4 (and the
+project's synthetic workloads) as parameter sets, initial velocity and
+pressure fields and grid metric arrays.  It holds none of the method's
+arithmetic, and both the HIP library and the CPU oracle consume exactly the
+arrays it produces.
+
+Conventions
+-----------
+* Fields are float64 arrays of shape (ny, nx), x fastest.
+* Periodic axes place nodes at x_i = i L / N; wall axes place nodes on both
+  walls, x_i = X(i/(N-1)), so the uniform wall spacing is L/(N-1).
+* A mapped axis x = X(xi), xi in [0, 1], is described by the derivative scale
+  inv_dx[i] = 1 / (X'(xi_i) * dxi) and by the smallest node spacing dx_min.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+PERIODIC = 0
+WALL = 1
+
+
+@dataclasses.dataclass
+class Problem:
+    """One MDF-FDLBM run: parameters plus initial fields (u0, v0, p0)."""
+
+    nx: int
+    ny: int
+    lx: float
+    ly: float
+    nu: float                       # Newtonian nu, or consistency K if pl_n != 1
+    u0: np.ndarray
+    v0: np.ndarray
+    p0: np.ndarray
+    pl_n: float = 1.0
+    nu_min: float = 0.0
+    nu_max: float = 0.0
+    cfl: float = 0.5
+    c: float = 1.0
+    eta: float = 0.8
+    s_ratio: float = 1.5
+    bc_x: int = PERIODIC
+    bc_y: int = PERIODIC
+    lid_u: float = 0.0
+    fx: float = 0.0
+    fy: float = 0.0
+    inv_dx_x: Optional[np.ndarray] = None
+    inv_dx_y: Optional[np.ndarray] = None
+    dx_min: float = 0.0
+    name: str = ""
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny
+
+    def node_x(self) -> np.ndarray:
+        return _axis_nodes(self.nx, self.lx, self.bc_x)
+
+    def node_y(self) -> np.ndarray:
+        return _axis_nodes(self.ny, self.ly, self.bc_y)
+
+
+def _axis_nodes(n: int, length: float, bc: int) -> np.ndarray:
+    if bc == WALL:
+        return np.arange(n, dtype=np.float64) * (length / (n - 1))
+    return np.arange(n, dtype=np.float64) * (length / n)
+
+
+# ---------------------------------------------------------------------------
+# analytic set-ups of Sec. 4 and the project's workloads
+# ---------------------------------------------------------------------------
+
+def taylor_green(n: int = 64, u0: float = 0.01, nu: float = 0.01, cfl: float = 0.5,
+                 eta: float = 0.8, s_ratio: float = 1.5, length: float = 2.0 * math.pi) -> Problem:
+    """Decaying Taylor-Green vortex on a periodic [0, L]^2 grid (the unforced
+    sibling of the four-roll mill, Sec. 4.1):
+    u = u0 sin x cos y, v = -u0 cos x sin y, P = (u0^2/4)(cos 2x + cos 2y)."""
+    x = _axis_nodes(n, length, PERIODIC)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    k = 2.0 * math.pi / length
+    u = u0 * np.sin(k * X) * np.cos(k * Y)
+    v = -u0 * np.cos(k * X) * np.sin(k * Y)
+    p = 0.25 * u0 * u0 * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    return Problem(nx=n, ny=n, lx=length, ly=length, nu=nu, u0=u, v0=v, p0=p, cfl=cfl,
+                   eta=eta, s_ratio=s_ratio, name=f"taylor_green_{n}")
+
+
+def taylor_green_exact(prob: Problem, t: float, u0: float, nu: float):
+    """Analytic decaying Taylor-Green fields at time t (factor exp(-2 nu t))."""
+    x, y = prob.node_x(), prob.node_y()
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    k = 2.0 * math.pi / prob.lx
+    dec = math.exp(-2.0 * nu * k * k * t)
+    u = u0 * dec * np.sin(k * X) * np.cos(k * Y)
+    v = -u0 * dec * np.cos(k * X) * np.sin(k * Y)
+    p = 0.25 * u0 * u0 * dec * dec * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    return u, v, p
+
+
+def cavity(n: int = 1024, re: float = 1000.0, lid: float = 0.1, cfl: float = 0.5, eta: float = 0.8,
+           s_ratio: float = 1.5, length: float = 1.0) -> Problem:
+    """Lid-driven square cavity (Sec. 4.4): fluid at rest, u = 0 and p = 0,
+    top wall moving at `lid`, nu = L lid / Re, walls on all four sides."""
+    z = np.zeros((n, n))
+    return Problem(nx=n, ny=n, lx=length, ly=length, nu=length * lid / re, u0=z, v0=z.copy(), p0=z.copy(),
+                   cfl=cfl, eta=eta, s_ratio=s_ratio, bc_x=WALL, bc_y=WALL, lid_u=lid,
+                   name=f"cavity_{n}_re{re:g}")
+
+
+def poiseuille(n: int = 32, nu: float = 0.01, force: float = 1e-6, cfl: float = 0.5, eta: float = 0.8,
+               s_ratio: float = 1.5, pl_n: float = 1.0, nu_min: float = 0.0, nu_max: float = 0.0,
+               inv_dx_y: Optional[np.ndarray] = None, dx_min: float = 0.0) -> Problem:
+    """Force-driven channel (Sec. 4.3): [0,1]^2, periodic in x, walls at
+    y = 0 and y = 1, fluid at rest initially."""
+    z = np.zeros((n, n))
+    return Problem(nx=n, ny=n, lx=1.0, ly=1.0, nu=nu, u0=z, v0=z.copy(), p0=z.copy(), cfl=cfl, eta=eta,
+                   s_ratio=s_ratio, bc_x=PERIODIC, bc_y=WALL, fx=force, pl_n=pl_n, nu_min=nu_min,
+                   nu_max=nu_max, inv_dx_y=inv_dx_y, dx_min=dx_min, name=f"poiseuille_{n}")
+
+
+def poiseuille_exact(y: np.ndarray, nu: float, force: float, height: float = 1.0) -> np.ndarray:
+    """Newtonian channel profile (eq. 4.3.1): u = F H^2/(2 nu) [y/H - (y/H)^2]."""
+    return force * height * height / (2.0 * nu) * (y / height - (y / height) ** 2)
+
+
+def powerlaw_poiseuille_exact(y: np.ndarray, pl_n: float, K: float, force: float, height: float = 1.0):
+    """Steady power-law channel profile for nu = K gdot^(n-1):
+    u(y) = n/(n+1) (F/K)^(1/n) [(H/2)^(1+1/n) - |y - H/2|^(1+1/n)]."""
+    e = 1.0 + 1.0 / pl_n
+    return pl_n / (pl_n + 1.0) * (force / K) ** (1.0 / pl_n) * ((height / 2) ** e - np.abs(y - height / 2) ** e)
+
+
+def tanh_mapping(n: int, beta: float = 1.5, length: float = 1.0):
+    """Wall-clustering map X(xi) = L/2 [1 + tanh(beta (2 xi - 1)) / tanh(beta)]
+    on nodes xi_i = i/(n-1).  Returns (node positions, inv_dx, dx_min)."""
+    xi = np.arange(n, dtype=np.float64) / (n - 1)
+    tb = math.tanh(beta)
+    pos = 0.5 * length * (1.0 + np.tanh(beta * (2.0 * xi - 1.0)) / tb)
+    dX = length * beta / tb / np.cosh(beta * (2.0 * xi - 1.0)) ** 2   # X'(xi)
+    inv_dx = 1.0 / (dX * (1.0 / (n - 1)))
+    dx_min = float(np.min(np.diff(pos)))
+    return pos, inv_dx, dx_min
+
+
+def sine_mapping(n: int, amp: float = 0.2, length: float = 2.0 * math.pi):
+    """Smooth periodic map X(xi) = xi + amp sin(xi) on xi_i = i L/n (amp < 1).
+    Returns (node positions, inv_dx, dx_min)."""
+    xi = np.arange(n, dtype=np.float64) * (length / n)
+    k = 2.0 * math.pi / length
+    pos = xi + amp * np.sin(k * xi) / k
+    dX = 1.0 + amp * np.cos(k * xi)
+    inv_dx = 1.0 / (dX * (length / n))
+    d = np.diff(np.concatenate([pos, [pos[0] + length]]))
+    return pos, inv_dx, float(np.min(d))
+
+
+def powerlaw_cavity(n: int = 2048, pl_n: float = 0.5, beta: float = 1.5, lid: float = 0.1,
+                    re: float = 100.0, cfl: float = 0.5, eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+    """Power-law lid-driven cavity on a tanh-stretched grid (both axes).
+    Re = U^(2-n) L^n / K with L = 1; viscosity clamp [1e-2, 1e2] nu_ref with
+    nu_ref = U L / Re."""
+    K = lid ** (2.0 - pl_n) / re
+    nu_ref = lid / re
+    _, g, dxm = tanh_mapping(n, beta)
+    z = np.zeros((n, n))
+    return Problem(nx=n, ny=n, lx=1.0, ly=1.0, nu=K, u0=z, v0=z.copy(), p0=z.copy(), pl_n=pl_n,
+                   nu_min=1e-2 * nu_ref, nu_max=1e2 * nu_ref, cfl=cfl, eta=eta, s_ratio=s_ratio,
+                   bc_x=WALL, bc_y=WALL, lid_u=lid, inv_dx_x=g.copy(), inv_dx_y=g.copy(), dx_min=dxm,
+                   name=f"powerlaw_cavity_{n}_n{pl_n:g}")
+
+
+def random_vortex_fields(n: int, seed: int, kmin: int = 1, kmax: int = 8, urms: float = 0.02,
+                         length: float = 2.0 * math.pi):
+    """Random-phase periodic velocity field with streamfunction modes
+    kmin <= |k| <= kmax, |psi_hat(k)| ~ |k|^-3 (energy spectrum ~ k^-3), scaled
+    to the given rms speed.  Fields are direct mode sums evaluated on the node
+    positions, so every n samples the same continuous field; the pressure
+    solves the Poisson equation lap P = -div(u . grad u) spectrally on the
+    mode set (host-side set-up of a consistent initial pressure)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    modes = []
+    for kx in range(-kmax, kmax + 1):
+        for ky in range(0, kmax + 1):
+            if ky == 0 and kx <= 0:
+                continue
+            kk = math.hypot(kx, ky)
+            if kk < kmin or kk > kmax:
+                continue
+            modes.append((kx, ky, kk))
+    phases = rng.uniform(0.0, 2.0 * math.pi, size=len(modes))
+    x = _axis_nodes(n, length, PERIODIC)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    k0 = 2.0 * math.pi / length
+    u = np.zeros((n, n))
+    v = np.zeros((n, n))
+    for (kx, ky, kk), ph in zip(modes, phases):
+        amp = kk ** -3.0
+        arg = k0 * (kx * X + ky * Y) + ph
+        # psi = amp cos(arg): u = d psi/dy, v = -d psi/dx
+        s = np.sin(arg)
+        u += -amp * k0 * ky * s
+        v += amp * k0 * kx * s
+    scale = urms / math.sqrt(np.mean(u * u + v * v))
+    u *= scale
+    v *= scale
+    # pressure: lap P = -d_i d_j (u_i u_j), solved with an FFT on the grid
+    kvec = np.fft.fftfreq(n, d=1.0 / n) * k0
+    KX, KY = np.meshgrid(kvec, kvec, indexing="xy")
+    k2 = KX * KX + KY * KY
+    k2[0, 0] = 1.0
+    uu, uv, vv = np.fft.fft2(u * u), np.fft.fft2(u * v), np.fft.fft2(v * v)
+    rhs = -(-(KX * KX) * uu - 2.0 * KX * KY * uv - (KY * KY) * vv)
+    ph = rhs / (-k2)
+    ph[0, 0] = 0.0
+    p = np.real(np.fft.ifft2(ph))
+    return u, v, p
+
+
+def random_vortex(n: int, seed: int, nu: float, kmin: int = 1, kmax: int = 8, urms: float = 0.02,
+                  cfl: float = 0.5, eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+    u, v, p = random_vortex_fields(n, seed, kmin, kmax, urms)
+    L = 2.0 * math.pi
+    return Problem(nx=n, ny=n, lx=L, ly=L, nu=nu, u0=u, v0=v, p0=p, cfl=cfl, eta=eta, s_ratio=s_ratio,
+                   name=f"random_vortex_{n}_s{seed}")
+
+
+def batch_instances(count: int = 256, seed: int = 20230614, sizes: Sequence[int] = (64, 128, 256, 512),
+                    log_nu: tuple = (-3.0, -1.0), kmax: int = 8, urms: float = 0.02,
+                    field_seed_base: int = 100000):
+    """Batched workload: `count` periodic decaying-vortex instances with grid
+    sizes uniform over `sizes` and nu log-uniform in 10^log_nu, drawn from a
+    PCG64 stream with the given seed.  Returns a list of (n, nu, field_seed);
+    fields come from random_vortex(n, field_seed, nu)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.choice(np.asarray(sizes), size=count)
+    nus = 10.0 ** rng.uniform(log_nu[0], log_nu[1], size=count)
+    return [(int(ns[i]), float(nus[i]), field_seed_base + i) for i in range(count)]
+
+
+def gre(phi: np.ndarray, exact: np.ndarray) -> float:
+    """Global relative error of eq. 4.0: sum |phi - phi*| / sum |phi*|."""
+    return float(np.sum(np.abs(phi - exact)) / np.sum(np.abs(exact)))
