@@ -1,0 +1,150 @@
+"""Benchmark of the MDF-FDLBM FP64 time step on one MI355X.
+
+Workload: lid-driven square cavity, Re = 1000, 1024 x 1024 nodes (walls
+included), lid speed 0.1, fluid at rest initially, FP64 throughout.  A "step"
+is one full time step of the method (Steps (1)-(4) of Sec. 2.2 with walls).
+
+Prints one JSON line with MLUPS (= nodes x steps / s / 1e6), the roofline of
+the fused step kernel (algorithmic 160 B per node and step: one read and one
+write of the ten FP64 distribution planes) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+BYTES_PER_NODE = 160.0         # 10 FP64 planes read + 10 written per node and step
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_cavity1024_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2306_08216_amd", "csrc", "mdf_fused.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in (KERNEL_SRC, os.path.join(ROOT, "paper_2306_08216_amd", "csrc", "mdf_device.hpp")):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_sha = re.search(r"kernel_sha:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or m_sha.group(1) != kernel_sha():
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(prob, steps):
+    """The CPU oracle (single thread, as it stands) on `steps` steps of the same workload."""
+    from oracle.orc import Oracle
+    o = Oracle(prob)
+    o.step(1)
+    t0 = time.perf_counter()
+    o.step(steps)
+    el = time.perf_counter() - t0
+    return prob.nodes * steps / el / 1e6, el
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=1024, help="nodes per side")
+    ap.add_argument("--tile-w", type=int, default=0)
+    ap.add_argument("--seg-h", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for the CPU baseline (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2306_08216_amd import problems as P
+    from paper_2306_08216_amd.solver import Solver
+
+    prob = P.cavity(args.n, re=1000.0, lid=0.1)
+    dev = torch.device("cuda:0")
+    s = Solver(prob, device="cuda:0")
+    if args.variant != 1 or args.tile_w or args.seg_h:
+        s.set_kernel(args.variant, args.tile_w, args.seg_h)
+    stream = s.stream
+
+    s.step(args.warmup)
+    torch.cuda.synchronize(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    diag, status = s.diagnostics()
+    if status != 0:
+        log(f"warning: diagnostics status {status}: {diag}")
+
+    nodes = prob.nodes
+    sec = gpu_ms / 1e3
+    mlups = nodes * args.steps / sec / 1e6
+    launch_s = sec / args.steps            # one fused launch per step (+1 wall-rule launch per call)
+    achieved = BYTES_PER_NODE * nodes / launch_s / 1e9
+    traffic = measured_traffic()
+
+    cpu = None
+    if args.cpu_steps > 0:
+        small = P.cavity(args.n, re=1000.0, lid=0.1)
+        v, el = cpu_baseline(small, args.cpu_steps)
+        cpu = {"value": round(v, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_steps} steps of the {args.n}x{args.n} cavity after 1 untimed step "
+                         f"({el:.1f} s, single-threaded C oracle, -O2 -ffp-contract=off)"}
+
+    out = {
+        "metric": "MLUPS (FP64) + % HBM roofline",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lid-driven cavity Re=1000, {args.n}x{args.n} nodes, lid 0.1, from rest, FP64",
+                   "kernel": "fused" if args.variant == 1 else "three-pass",
+                   "wall_s": round(wall, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,134 @@
+/*
+ * mdf.h -- C ABI of the MI355X MDF-FDLBM library (libmdf.so).
+ *
+ * The library advances the multiple-distribution-function finite-difference
+ * lattice Boltzmann method (Chen, Chai, Zhao & Shi) for the incompressible
+ * Navier-Stokes equations written as the convection-diffusion system of
+ * eq. 2.1.2, on a 2D grid, in FP64, on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All arrays are FP64 and, unless a call says otherwise, DEVICE memory.
+ *  - A field is ny*nx values, x fastest:  a[y*nx + x].
+ *  - A distribution array is 10 fields, plane index alpha*5 + j with
+ *    alpha = 0 (u equation), 1 (v equation) and the D2Q5 velocities
+ *    c_j = c*{(0,0),(1,0),(0,1),(-1,0),(0,-1)} of eq. 3.1.0.
+ *  - Periodic axes place nodes at x_i = i*L/N; wall axes put nodes on both
+ *    walls, x_i = X(i/(N-1)).
+ *  - The caller owns all device memory.  mdf_init carves the caller's
+ *    workspace (at least mdf_workspace_size bytes, 256-byte aligned) and
+ *    keeps using it until mdf_destroy; the caller keeps it alive that long.
+ *  - Calls that take an mdf_ctx enqueue work on the context's HIP stream
+ *    and return without waiting, except where a call says it synchronises.
+ *  - No call throws or aborts.  Every call returns an mdf_status; a short
+ *    description of the last failure is available from mdf_last_error.
+ *    A call that returns an error leaves the context's state unchanged
+ *    unless it says otherwise.
+ */
+#ifndef MDF_H
+#define MDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdf_ctx mdf_ctx;
+
+typedef enum {
+    MDF_OK = 0,
+    MDF_EINVAL = -1,    /* a parameter or argument is out of range            */
+    MDF_ESTATE = -2,    /* the context cannot do this now                      */
+    MDF_EDEVICE = -3,   /* a HIP runtime call failed                           */
+    MDF_EUNSTABLE = -4  /* diagnostics found a non-finite value in the state   */
+} mdf_status;
+
+typedef enum { MDF_BC_PERIODIC = 0, MDF_BC_WALL = 1 } mdf_bc;
+
+/* Problem parameters (Sec. 2 and the set-ups of Sec. 4).  Host memory. */
+typedef struct {
+    int32_t nx, ny;          /* nodes per axis; >= 5 on every axis (wall axes include the wall nodes) */
+    double  lx, ly;          /* domain lengths                                                     */
+    double  nu;              /* kinematic viscosity nu = c_s^2/s (eq. 2.3.14); the consistency K
+                                of the power law when pl_n != 1                                     */
+    double  pl_n;            /* power-law index: 1 (Newtonian), 0.5 or 1.5                          */
+    double  nu_min, nu_max;  /* clamp of the local power-law viscosity (ignored when pl_n == 1)     */
+    double  cfl;             /* dt = cfl * dx_min / c (eq. 3.1)                                      */
+    double  c;               /* lattice speed |c_j|                                                  */
+    double  eta;             /* weight of the central part of the mixed scheme (eq. 2.2.12), [0,1]  */
+    double  s_ratio;         /* s'/s: rate of the non-conserved, non-flux moments (Sec. 3.1)        */
+    int32_t bc_x, bc_y;      /* mdf_bc per axis                                                      */
+    double  lid_u;           /* tangential speed of the wall at y = ly (corners excluded)           */
+    double  fx, fy;          /* uniform body force F_alpha (eq. 2.2.6)                               */
+    const double* inv_dx_x;  /* HOST, nx values: 1/(X'(xi_i) dxi) of a mapped x axis, or NULL (uniform) */
+    const double* inv_dx_y;  /* HOST, ny values, same for y, or NULL                                */
+    double  dx_min;          /* smallest node spacing; required when either metric array is given */
+} mdf_params;
+
+/* Bytes of device workspace a context for these parameters needs, or 0 if the
+ * parameters are invalid.  Depends only on nx and ny. */
+size_t mdf_workspace_size(const mdf_params* p);
+
+/* Create a context and initialise the state f_hat = f^eq(u0, v0, p0) of
+ * eq. 2.2.5 at every node (the initialisation of Sec. 4), then apply the wall
+ * rule so that wall nodes carry the wall velocity.
+ *   p          host parameters; metric arrays are copied, p may be freed after
+ *   u0,v0,p0   DEVICE fields (ny*nx, x fastest) of velocity and pressure
+ *   workspace  DEVICE memory of at least mdf_workspace_size(p) bytes, 256-byte aligned
+ *   ws_bytes   its size
+ *   hip_stream hipStream_t the context enqueues on (NULL = default stream)
+ *   out        receives the context
+ * Synchronises the stream before returning.  Returns MDF_EINVAL when nu <= 0,
+ * cfl <= 0, c <= 0, eta outside [0,1], an axis has fewer than 5 nodes, pl_n is
+ * not 1, 0.5 or 1.5, the power-law clamp is empty, metrics come without dx_min,
+ * or the workspace is too small or misaligned. */
+mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0,
+                    void* workspace, size_t ws_bytes, void* hip_stream, mdf_ctx** out);
+
+/* Advance n time steps of Sec. 2.2, Steps (1)-(4): collision at t (eqs. 2.2.14,
+ * 2.2.15), half step (eq. 2.3.25), collision at t+h (eq. 2.2.16) and full step
+ * (eq. 2.3.24), with the mixed difference of eqs. 2.2.12-2.2.13.  n >= 0. */
+mdf_status mdf_step(mdf_ctx* ctx, int64_t n);
+
+/* Velocity and pressure of the current state (eqs. 2.3.4 and 2.3.23 with R = 0)
+ * into caller-owned DEVICE fields (ny*nx each); any pointer may be NULL. */
+mdf_status mdf_moments(mdf_ctx* ctx, double* u, double* v, double* p);
+
+/* Local quantities from the first moment of the non-equilibrium part
+ * (Sec. 2.4, eqs. 2.4.1-2.4.5).  Bit k of mask selects plane k of the list
+ *   0 du/dx  1 du/dy  2 dv/dx  3 dv/dy  4 div u  5 Sxx  6 Sxy  7 Syy
+ *   8 sigma_xx  9 sigma_xy  10 sigma_yy  11 Omega_xy  12 vorticity  13 nu
+ * and the selected planes are written consecutively (in list order) to the
+ * DEVICE array out, ny*nx values each.  mask must be non-zero and < 2^14. */
+mdf_status mdf_derived(mdf_ctx* ctx, double* out, uint32_t mask);
+
+/* Diagnostics of the current state into HOST out[8]: sum u, sum v,
+ * KE = 1/2 sum |u|^2 dA, enstrophy = 1/2 sum omega^2 dA, max |u|, max |div u|
+ * by central differences over non-wall nodes, number of non-finite state
+ * values, sum dA (dA = node area).  Synchronises the stream.  Returns
+ * MDF_EUNSTABLE (with out filled) when the state holds a non-finite value. */
+mdf_status mdf_diagnostics(mdf_ctx* ctx, double out[8]);
+
+/* Copy the state out to / in from a caller-owned DEVICE distribution array
+ * (10*ny*nx values, layout above).  mdf_load replaces the state; the step
+ * counter is kept. */
+mdf_status mdf_save(mdf_ctx* ctx, double* f);
+mdf_status mdf_load(mdf_ctx* ctx, const double* f);
+
+/* Kernel selection for the time step: variant 0 = three-pass reference path,
+ * 1 = fused single-pass strip kernel (default).  tile_w (columns per
+ * workgroup, incl. the 8-column halo; 64, 128 or 256) and seg_h
+ * (rows per segment, >= 1) apply to variant 1; 0 keeps the current value. */
+mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t seg_h);
+
+double      mdf_dt(const mdf_ctx* ctx);          /* time step, or 0 for NULL       */
+int64_t     mdf_steps(const mdf_ctx* ctx);       /* steps taken since mdf_init     */
+const char* mdf_last_error(const mdf_ctx* ctx);  /* never NULL; "" when none       */
+void        mdf_destroy(mdf_ctx* ctx);           /* synchronises; NULL is a no-op  */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDF_H */

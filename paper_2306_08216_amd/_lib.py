@@ -1,0 +1,144 @@
+"""ctypes binding of libmdf.so: the C ABI of include/mdf.h under the same names.
+
+This module only marshals arguments.  It raises ImportError when the HIP
+library has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdf.so")
+
+MDF_OK, MDF_EINVAL, MDF_ESTATE, MDF_EDEVICE, MDF_EUNSTABLE = 0, -1, -2, -3, -4
+MDF_BC_PERIODIC, MDF_BC_WALL = 0, 1
+
+STATUS_NAMES = {0: "MDF_OK", -1: "MDF_EINVAL", -2: "MDF_ESTATE", -3: "MDF_EDEVICE", -4: "MDF_EUNSTABLE"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class mdf_params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("lx", C.c_double), ("ly", C.c_double),
+        ("nu", C.c_double),
+        ("pl_n", C.c_double), ("nu_min", C.c_double), ("nu_max", C.c_double),
+        ("cfl", C.c_double), ("c", C.c_double), ("eta", C.c_double), ("s_ratio", C.c_double),
+        ("bc_x", C.c_int32), ("bc_y", C.c_int32),
+        ("lid_u", C.c_double),
+        ("fx", C.c_double), ("fy", C.c_double),
+        ("inv_dx_x", _dp), ("inv_dx_y", _dp),
+        ("dx_min", C.c_double),
+    ]
+
+
+# every exported symbol of include/mdf.h, with (restype, argtypes)
+SIGNATURES = {
+    "mdf_workspace_size": (C.c_size_t, [C.POINTER(mdf_params)]),
+    "mdf_init": (C.c_int, [C.POINTER(mdf_params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                           C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mdf_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "mdf_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mdf_derived": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32]),
+    "mdf_diagnostics": (C.c_int, [C.c_void_p, _dp]),
+    "mdf_save": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mdf_load": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mdf_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "mdf_dt": (C.c_double, [C.c_void_p]),
+    "mdf_steps": (C.c_int64, [C.c_void_p]),
+    "mdf_last_error": (C.c_char_p, [C.c_void_p]),
+    "mdf_destroy": (None, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmdf.so (built by __graft_entry__.build()); fail loudly if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MdfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int, ctx=None):
+    if status != MDF_OK:
+        msg = lib().mdf_last_error(ctx)
+        raise MdfError(status, msg.decode() if msg else "")
+    return status
+
+
+# thin wrappers with the C names -------------------------------------------
+
+def mdf_workspace_size(p: mdf_params) -> int:
+    return lib().mdf_workspace_size(C.byref(p))
+
+
+def mdf_init(p: mdf_params, u0: int, v0: int, p0: int, workspace: int, ws_bytes: int, stream: int) -> int:
+    out = C.c_void_p()
+    check(lib().mdf_init(C.byref(p), u0, v0, p0, workspace, ws_bytes, stream, C.byref(out)))
+    return out.value
+
+
+def mdf_step(ctx: int, n: int):
+    return check(lib().mdf_step(ctx, int(n)), ctx)
+
+
+def mdf_moments(ctx: int, u: int, v: int, p: int):
+    return check(lib().mdf_moments(ctx, u, v, p), ctx)
+
+
+def mdf_derived(ctx: int, out: int, mask: int):
+    return check(lib().mdf_derived(ctx, out, int(mask)), ctx)
+
+
+def mdf_diagnostics(ctx: int, out8):
+    """out8: ctypes (c_double * 8). Returns the status (MDF_EUNSTABLE is returned, not raised)."""
+    s = lib().mdf_diagnostics(ctx, out8)
+    if s not in (MDF_OK, MDF_EUNSTABLE):
+        check(s, ctx)
+    return s
+
+
+def mdf_save(ctx: int, f: int):
+    return check(lib().mdf_save(ctx, f), ctx)
+
+
+def mdf_load(ctx: int, f: int):
+    return check(lib().mdf_load(ctx, f), ctx)
+
+
+def mdf_set_kernel(ctx: int, variant: int, tile_w: int = 0, seg_h: int = 0):
+    return check(lib().mdf_set_kernel(ctx, int(variant), int(tile_w), int(seg_h)), ctx)
+
+
+def mdf_dt(ctx: int) -> float:
+    return lib().mdf_dt(ctx)
+
+
+def mdf_steps(ctx: int) -> int:
+    return lib().mdf_steps(ctx)
+
+
+def mdf_last_error(ctx) -> str:
+    s = lib().mdf_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def mdf_destroy(ctx: int):
+    lib().mdf_destroy(ctx)

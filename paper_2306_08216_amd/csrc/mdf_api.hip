@@ -1,0 +1,353 @@
+// C ABI of the MDF-FDLBM library: parameter validation, constants of the
+// method, workspace carving and kernel launches.  See include/mdf.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/mdf.h"
+#include "mdf_internal.hpp"
+
+using mdf::StepConsts;
+
+struct mdf_ctx {
+    mdf_params p;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    double* f[2] = {nullptr, nullptr};
+    double* fbp = nullptr;
+    double* fmid = nullptr;
+    double* gx = nullptr;
+    double* gy = nullptr;
+    double* diag_part = nullptr;
+    double* diag_out = nullptr;
+    int cur = 0;
+    int64_t steps = 0;
+    int variant = 1;
+    mdf::FusedShape shape{256, 32};
+    StepConsts K;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+mdf_status fail(mdf_ctx* c, mdf_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    g_err = buf;
+    return s;
+}
+
+mdf_status hip_check(mdf_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MDF_OK;
+    return fail(c, MDF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct Layout {
+    size_t pitch, plane;          // doubles
+    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, total;  // bytes
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+Layout layout_for(int nx, int ny)
+{
+    Layout L;
+    L.pitch = ((size_t)nx + 15) & ~size_t(15);
+    // pad each plane by 512 B and round to 256 B so that the ten planes do not
+    // start at power-of-two strides from each other
+    L.plane = (L.pitch * (size_t)ny + 64 + 31) & ~size_t(31);
+    const size_t fbytes = align256(10 * L.plane * sizeof(double));
+    size_t o = 0;
+    L.off_f0 = o;   o += fbytes;
+    L.off_f1 = o;   o += fbytes;
+    L.off_fbp = o;  o += fbytes;
+    L.off_fmid = o; o += fbytes;
+    L.off_gx = o;   o += align256((size_t)nx * sizeof(double));
+    L.off_gy = o;   o += align256((size_t)ny * sizeof(double));
+    L.off_dp = o;   o += align256(8 * 1024 * sizeof(double));
+    L.off_do = o;   o += align256(8 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+const char* validate(const mdf_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->nx < 5 || p->ny < 5) return "nx and ny must be >= 5";
+    if ((long long)p->nx * p->ny > (1LL << 31)) return "grid too large (nx*ny > 2^31)";
+    if (!(p->lx > 0.0) || !(p->ly > 0.0)) return "lx and ly must be > 0";
+    if (!(p->nu > 0.0)) return "nu must be > 0";
+    if (!(p->cfl > 0.0)) return "cfl must be > 0";
+    if (!(p->c > 0.0)) return "c must be > 0";
+    if (!(p->eta >= 0.0 && p->eta <= 1.0)) return "eta must lie in [0, 1]";
+    if (!(p->s_ratio > 0.0)) return "s_ratio must be > 0";
+    if (p->bc_x != MDF_BC_PERIODIC && p->bc_x != MDF_BC_WALL) return "bc_x must be MDF_BC_PERIODIC or MDF_BC_WALL";
+    if (p->bc_y != MDF_BC_PERIODIC && p->bc_y != MDF_BC_WALL) return "bc_y must be MDF_BC_PERIODIC or MDF_BC_WALL";
+    if (!(p->pl_n == 1.0 || p->pl_n == 0.5 || p->pl_n == 1.5)) return "pl_n must be 1, 0.5 or 1.5";
+    if (p->pl_n != 1.0 && !(p->nu_min > 0.0 && p->nu_max >= p->nu_min)) return "power law needs 0 < nu_min <= nu_max";
+    if ((p->inv_dx_x || p->inv_dx_y) && !(p->dx_min > 0.0)) return "metric arrays need dx_min > 0";
+    if (!std::isfinite(p->fx) || !std::isfinite(p->fy) || !std::isfinite(p->lid_u)) return "non-finite force or lid speed";
+    return nullptr;
+}
+
+// Constants of the method for one run (Sec. 2.2; eq. 3.1 for dt).
+StepConsts make_consts(const mdf_params& p, const Layout& L)
+{
+    StepConsts K{};
+    K.nx = p.nx;
+    K.ny = p.ny;
+    K.bcx = p.bc_x;
+    K.bcy = p.bc_y;
+    K.pl = p.pl_n == 1.0 ? mdf::PL_NEWTON : (p.pl_n == 0.5 ? mdf::PL_HALF : mdf::PL_THREE_HALVES);
+    K.pitch = (int)L.pitch;
+    K.plane = (long long)L.plane;
+    K.c = p.c;
+    K.w = 0.2;                                  // D2Q5 weights 1/5
+    K.cs2 = 0.4 * p.c * p.c;                    // sum_j w_j c_jx^2 = 2c^2/5
+    K.kf = K.w * p.c / K.cs2;
+    const double hx = p.bc_x == MDF_BC_WALL ? p.lx / (p.nx - 1) : p.lx / p.nx;
+    const double hy = p.bc_y == MDF_BC_WALL ? p.ly / (p.ny - 1) : p.ly / p.ny;
+    const double dxmin = (p.inv_dx_x || p.inv_dx_y) ? p.dx_min : (hx < hy ? hx : hy);
+    K.dt = p.cfl * dxmin / p.c;
+    K.h = 0.5 * K.dt;
+    K.eta = p.eta;
+    K.one_m_eta = 1.0 - p.eta;
+    K.st_a = 1.0 - p.eta;
+    K.st_b = -(4.0 - 3.0 * p.eta);
+    K.st_c = 3.0 * (1.0 - p.eta);
+    K.st_d = p.eta;
+    K.lid_u = p.lid_u;
+    K.nu = p.nu;
+    K.nu_min = p.nu_min;
+    K.nu_max = p.nu_max;
+    K.s_ratio = p.s_ratio;
+    K.theta1 = 0.5 * K.cs2 * K.dt;
+    K.theta3 = 0.25 * K.cs2 * K.dt;
+    const double s = K.cs2 / p.nu, sp = p.s_ratio * s;
+    auto a = [&](double sig) { return (1.0 - 0.5 * sig * K.dt) / (1.0 + 0.5 * sig * K.dt); };
+    K.a_s = a(s);
+    K.a_p = a(sp);
+    K.b_s = 0.25 * (1.0 + 3.0 * K.a_s);
+    K.b_p = 0.25 * (1.0 + 3.0 * K.a_p);
+    K.q_s = 1.0 / (1.0 + 0.25 * s * K.dt);
+    K.q_p = 1.0 / (1.0 + 0.25 * sp * K.dt);
+    K.lam_h = 0.5 * K.h * p.c;
+    K.lam_dt = 0.5 * K.dt * p.c;
+    K.hwf[0] = K.h * K.w * p.fx;
+    K.hwf[1] = K.h * K.w * p.fy;
+    K.dwf[0] = K.dt * K.w * p.fx;
+    K.dwf[1] = K.dt * K.w * p.fy;
+    return K;
+}
+
+mdf::FusedShape default_shape(const mdf_params& p)
+{
+    mdf::FusedShape sh;
+    sh.tile_w = p.nx >= 960 ? 256 : (p.nx >= 240 ? 128 : 64);
+    const int nstrips = (p.nx + sh.tile_w - 9) / (sh.tile_w - 8);
+    // aim at about 1024 workgroups, with segments of at least 8 rows
+    int nseg = 1024 / (nstrips > 0 ? nstrips : 1);
+    if (nseg < 1) nseg = 1;
+    int h = (p.ny + nseg - 1) / nseg;
+    if (h < 8) h = 8;
+    sh.seg_h = h;
+    return sh;
+}
+
+bool check_ctx(mdf_ctx* c) { return c != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+size_t mdf_workspace_size(const mdf_params* p)
+{
+    if (validate(p)) return 0;
+    return layout_for(p->nx, p->ny).total;
+}
+
+mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0, void* workspace,
+                    size_t ws_bytes, void* hip_stream, mdf_ctx** out)
+{
+    if (!out) return fail(nullptr, MDF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (const char* why = validate(p)) return fail(nullptr, MDF_EINVAL, "%s", why);
+    if (!u0 || !v0 || !p0) return fail(nullptr, MDF_EINVAL, "initial fields must be non-NULL device pointers");
+    const Layout L = layout_for(p->nx, p->ny);
+    if (!workspace || ws_bytes < L.total)
+        return fail(nullptr, MDF_EINVAL, "workspace too small: need %zu bytes, got %zu", L.total, ws_bytes);
+    if (((uintptr_t)workspace & 255u) != 0) return fail(nullptr, MDF_EINVAL, "workspace must be 256-byte aligned");
+
+    mdf_ctx* c = new (std::nothrow) mdf_ctx();
+    if (!c) return fail(nullptr, MDF_EDEVICE, "out of host memory");
+    c->p = *p;
+    c->p.inv_dx_x = nullptr;
+    c->p.inv_dx_y = nullptr;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)workspace;
+    c->ws_bytes = ws_bytes;
+    c->f[0] = (double*)(c->ws + L.off_f0);
+    c->f[1] = (double*)(c->ws + L.off_f1);
+    c->fbp = (double*)(c->ws + L.off_fbp);
+    c->fmid = (double*)(c->ws + L.off_fmid);
+    c->gx = (double*)(c->ws + L.off_gx);
+    c->gy = (double*)(c->ws + L.off_gy);
+    c->diag_part = (double*)(c->ws + L.off_dp);
+    c->diag_out = (double*)(c->ws + L.off_do);
+    c->K = make_consts(*p, L);
+    c->K.gx = c->gx;
+    c->K.gy = c->gy;
+    c->shape = default_shape(*p);
+
+    // derivative scales 1/(X' dxi) per node (uniform: 1/dx)
+    std::string hbuf;
+    {
+        const double hx = p->bc_x == MDF_BC_WALL ? p->lx / (p->nx - 1) : p->lx / p->nx;
+        const double hy = p->bc_y == MDF_BC_WALL ? p->ly / (p->ny - 1) : p->ly / p->ny;
+        double* gxh = new (std::nothrow) double[(size_t)p->nx + p->ny];
+        if (!gxh) {
+            delete c;
+            return fail(nullptr, MDF_EDEVICE, "out of host memory");
+        }
+        for (int i = 0; i < p->nx; ++i) gxh[i] = p->inv_dx_x ? p->inv_dx_x[i] : 1.0 / hx;
+        for (int i = 0; i < p->ny; ++i) gxh[p->nx + i] = p->inv_dx_y ? p->inv_dx_y[i] : 1.0 / hy;
+        for (int i = 0; i < p->nx + p->ny; ++i)
+            if (!(gxh[i] > 0.0) || !std::isfinite(gxh[i])) {
+                delete[] gxh;
+                delete c;
+                return fail(nullptr, MDF_EINVAL, "metric arrays must be finite and > 0");
+            }
+        hipError_t e = hipMemcpyAsync(c->gx, gxh, sizeof(double) * p->nx, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->gy, gxh + p->nx, sizeof(double) * p->ny, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        delete[] gxh;
+        if (e != hipSuccess) {
+            mdf_status s = hip_check(nullptr, e, "metric upload");
+            delete c;
+            return s;
+        }
+    }
+    hipError_t e = mdf::launch_init(c->K, u0, v0, p0, c->f[0], c->stream);
+    if (e == hipSuccess) e = mdf::launch_wall_fix(c->K, c->f[0], c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        mdf_status s = hip_check(nullptr, e, "initialisation");
+        delete c;
+        return s;
+    }
+    *out = c;
+    return MDF_OK;
+}
+
+mdf_status mdf_step(mdf_ctx* c, int64_t n)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(c, MDF_EINVAL, "n must be >= 0");
+    if (n == 0) return MDF_OK;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* fin = c->f[c->cur];
+        double* fout = c->f[1 - c->cur];
+        hipError_t e;
+        if (c->variant == 0)
+            e = mdf::launch_three_pass(c->K, fin, c->fbp, c->fmid, fout, c->stream);
+        else
+            e = mdf::launch_fused(c->K, c->shape, fin, fout, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "step launch");
+        c->cur = 1 - c->cur;
+        c->steps += 1;
+    }
+    if (c->variant != 0) {
+        hipError_t e = mdf::launch_wall_fix(c->K, c->f[c->cur], c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "wall rule launch");
+    }
+    return MDF_OK;
+}
+
+mdf_status mdf_moments(mdf_ctx* c, double* u, double* v, double* p)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!u && !v && !p) return MDF_OK;
+    return hip_check(c, mdf::launch_moments(c->K, c->f[c->cur], u, v, p, c->stream), "moments launch");
+}
+
+mdf_status mdf_derived(mdf_ctx* c, double* out, uint32_t mask)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!out) return fail(c, MDF_EINVAL, "out is NULL");
+    if (mask == 0 || mask >= (1u << 14)) return fail(c, MDF_EINVAL, "mask must be in [1, 2^14)");
+    return hip_check(c, mdf::launch_derived(c->K, c->f[c->cur], out, mask, c->stream), "derived launch");
+}
+
+mdf_status mdf_diagnostics(mdf_ctx* c, double out[8])
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!out) return fail(c, MDF_EINVAL, "out is NULL");
+    hipError_t e = mdf::launch_diagnostics(c->K, c->f[c->cur], c->diag_part, c->diag_out, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, c->diag_out, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "diagnostics");
+    if (out[6] != 0.0) return fail(c, MDF_EUNSTABLE, "state holds %.0f non-finite values", out[6]);
+    return MDF_OK;
+}
+
+mdf_status mdf_save(mdf_ctx* c, double* f)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!f) return fail(c, MDF_EINVAL, "f is NULL");
+    return hip_check(c, mdf::launch_pack(c->K, c->f[c->cur], f, c->stream), "save launch");
+}
+
+mdf_status mdf_load(mdf_ctx* c, const double* f)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!f) return fail(c, MDF_EINVAL, "f is NULL");
+    return hip_check(c, mdf::launch_unpack(c->K, f, c->f[c->cur], c->stream), "load launch");
+}
+
+mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t seg_h)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (variant != 0 && variant != 1) return fail(c, MDF_EINVAL, "variant must be 0 or 1");
+    mdf::FusedShape sh = c->shape;
+    if (tile_w) sh.tile_w = tile_w;
+    if (seg_h) sh.seg_h = seg_h;
+    if (!mdf::fused_shape_ok(c->K, sh))
+        return fail(c, MDF_EINVAL, "tile_w must be 64, 128 or 256 and seg_h >= 1");
+    c->variant = variant;
+    c->shape = sh;
+    return MDF_OK;
+}
+
+double mdf_dt(const mdf_ctx* c) { return c ? c->K.dt : 0.0; }
+
+int64_t mdf_steps(const mdf_ctx* c) { return c ? c->steps : 0; }
+
+const char* mdf_last_error(const mdf_ctx* c)
+{
+    if (c) return c->err.c_str();
+    return g_err.c_str();
+}
+
+void mdf_destroy(mdf_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// Auxiliary kernels: initialisation, wall rule on a stored field, moments,
+// local derived quantities, diagnostics reductions, plane copies, and the
+// three-pass reference time step (one kernel per sub-step of Sec. 2.2).
+#include "mdf_device.hpp"
+#include "mdf_internal.hpp"
+
+namespace mdf {
+
+namespace {
+
+__device__ __forceinline__ long long nidx(const StepConsts& K, int x, int y) { return (long long)y * K.pitch + x; }
+
+__device__ __forceinline__ void load10(const StepConsts& K, const double* f, long long i, double* phi)
+{
+#pragma unroll
+    for (int k = 0; k < 10; ++k) phi[k] = f[k * K.plane + i];
+}
+
+__device__ __forceinline__ void store10(const StepConsts& K, double* f, long long i, const double* phi)
+{
+#pragma unroll
+    for (int k = 0; k < 10; ++k) f[k * K.plane + i] = phi[k];
+}
+
+// inward neighbours of a wall node; returns false for interior nodes
+__device__ __forceinline__ bool wall_neighbours(const StepConsts& K, int x, int y, int& x1, int& y1, int& x2, int& y2,
+                                                double& uw)
+{
+    int ix = 0, iy = 0;
+    if (K.bcx) ix = (x == 0) ? 1 : (x == K.nx - 1 ? -1 : 0);
+    if (K.bcy) iy = (y == 0) ? 1 : (y == K.ny - 1 ? -1 : 0);
+    if (ix == 0 && iy == 0) return false;
+    const bool corner = ix != 0 && iy != 0;
+    uw = (K.bcy && y == K.ny - 1 && !corner) ? K.lid_u : 0.0;
+    x1 = x + ix;
+    y1 = y + iy;
+    x2 = x + 2 * ix;
+    y2 = y + 2 * iy;
+    return true;
+}
+
+// value of one plane at (x, y) where one coordinate may be one node beyond a
+// wall (quadratic ghost) or outside a periodic range (wrapped)
+__device__ __forceinline__ double fetch(const StepConsts& K, const double* pl, int x, int y)
+{
+    if (!K.bcx) x = x < 0 ? x + K.nx : (x >= K.nx ? x - K.nx : x);
+    if (!K.bcy) y = y < 0 ? y + K.ny : (y >= K.ny ? y - K.ny : y);
+    if (x == -1) return ghost(pl[nidx(K, 0, y)], pl[nidx(K, 1, y)], pl[nidx(K, 2, y)]);
+    if (x == K.nx) return ghost(pl[nidx(K, K.nx - 1, y)], pl[nidx(K, K.nx - 2, y)], pl[nidx(K, K.nx - 3, y)]);
+    if (y == -1) return ghost(pl[nidx(K, x, 0)], pl[nidx(K, x, 1)], pl[nidx(K, x, 2)]);
+    if (y == K.ny) return ghost(pl[nidx(K, x, K.ny - 1)], pl[nidx(K, x, K.ny - 2)], pl[nidx(K, x, K.ny - 3)]);
+    return pl[nidx(K, x, y)];
+}
+
+// tau c_j . grad Pi_j at an interior node (lam = tau c / 2)
+__device__ __forceinline__ double transport_at(const StepConsts& K, const double* f, int plane_k, int x, int y,
+                                               double lam)
+{
+    const int j = plane_k % 5;
+    const double* pl = f + plane_k * K.plane;
+    if (j == 0) return 0.0;
+    if (j == 1 || j == 3) {
+        const double lg = lam * K.gx[x];
+        const double pm1 = fetch(K, pl, x - 1, y), p0 = fetch(K, pl, x, y), p1 = fetch(K, pl, x + 1, y);
+        if (j == 1) return transport_pos(K, lg, fetch(K, pl, x - 2, y), pm1, p0, p1);
+        return transport_neg(K, lg, pm1, p0, p1, fetch(K, pl, x + 2, y));
+    }
+    const double lg = lam * K.gy[y];
+    const double pm1 = fetch(K, pl, x, y - 1), p0 = fetch(K, pl, x, y), p1 = fetch(K, pl, x, y + 1);
+    if (j == 2) return transport_pos(K, lg, fetch(K, pl, x, y - 2), pm1, p0, p1);
+    return transport_neg(K, lg, pm1, p0, p1, fetch(K, pl, x, y + 2));
+}
+
+__global__ void k_init(StepConsts K, const double* __restrict__ u0, const double* __restrict__ v0,
+                       const double* __restrict__ p0, double* __restrict__ f)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    const long long s = (long long)y * K.nx + x;
+    double fe[10];
+    equilibrium(u0[s], v0[s], p0[s], K, fe);
+    store10(K, f, nidx(K, x, y), fe);
+}
+
+// wall rule applied to the wall nodes of a stored 10-plane field
+__global__ void k_wall_fix(StepConsts K, double* __restrict__ f)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    int x1, y1, x2, y2;
+    double uw;
+    if (!wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) return;
+    double p1[10], p2[10], out[10];
+    load10(K, f, nidx(K, x1, y1), p1);
+    load10(K, f, nidx(K, x2, y2), p2);
+    wall_extrapolate(K, p1, p2, uw, out);
+    store10(K, f, nidx(K, x, y), out);
+}
+
+__global__ void k_moments(StepConsts K, const double* __restrict__ f, double* __restrict__ u, double* __restrict__ v,
+                          double* __restrict__ p)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    double phi[10], uu, vv, PP;
+    load10(K, f, nidx(K, x, y), phi);
+    node_moments(phi, K.c, uu, vv, PP);
+    const long long s = (long long)y * K.nx + x;
+    if (u) u[s] = uu;
+    if (v) v[s] = vv;
+    if (p) p[s] = PP;
+}
+
+// Local derived quantities (Sec. 2.4) at one node: out[14] in the list order of mdf.h.
+// M(f - f^eq) = M(f_hat - f^eq)/(1 + s dt/2), so eq. 2.4.1 reads
+// grad_b u_a = -sum_j c_{j,b} (f_hat - f^eq)_{j,a} / (nu + c_s^2 dt/2).
+__device__ __forceinline__ void derived_node(const StepConsts& K, const double* fh, double* out)
+{
+    double u, v, P, fe[10];
+    node_moments(fh, K.c, u, v, P);
+    equilibrium(u, v, P, K, fe);
+    const double nu = K.pl == PL_NEWTON ? K.nu : powerlaw_nu(K, noneq_shear(fh, fe, K.c), K.theta1);
+    const double inv = -K.c / (nu + K.theta1);
+    const double ux = inv * ((fh[1] - fe[1]) - (fh[3] - fe[3]));
+    const double uy = inv * ((fh[2] - fe[2]) - (fh[4] - fe[4]));
+    const double vx = inv * ((fh[6] - fe[6]) - (fh[8] - fe[8]));
+    const double vy = inv * ((fh[7] - fe[7]) - (fh[9] - fe[9]));
+    const double sxy = 0.5 * (uy + vx);
+    out[0] = ux;
+    out[1] = uy;
+    out[2] = vx;
+    out[3] = vy;
+    out[4] = ux + vy;
+    out[5] = ux;
+    out[6] = sxy;
+    out[7] = vy;
+    out[8] = 2.0 * nu * ux;
+    out[9] = 2.0 * nu * sxy;
+    out[10] = 2.0 * nu * vy;
+    out[11] = 0.5 * (uy - vx);
+    out[12] = vx - uy;
+    out[13] = nu;
+}
+
+__global__ void k_derived(StepConsts K, const double* __restrict__ f, double* __restrict__ out, uint32_t mask)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    double fh[10], d[14];
+    load10(K, f, nidx(K, x, y), fh);
+    derived_node(K, fh, d);
+    const long long n = (long long)K.nx * K.ny, s = (long long)y * K.nx + x;
+    int slot = 0;
+#pragma unroll
+    for (int k = 0; k < 14; ++k)
+        if (mask & (1u << k)) out[(slot++) * n + s] = d[k];
+}
+
+// ---- diagnostics: per-block partials in fixed order, then one block ----
+
+constexpr int DIAG_BLOCK = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ void block_reduce8(double* vals, double* part)
+{
+    __shared__ double red[DIAG_BLOCK / 64][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool mx = (k == 4 || k == 5);
+        const double r = mx ? wave_max(vals[k]) : wave_sum(vals[k]);
+        if (lane == 0) red[wv][k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = threadIdx.x;
+        const bool mx = (k == 4 || k == 5);
+        double acc = red[0][k];
+        for (int i = 1; i < DIAG_BLOCK / 64; ++i) acc = mx ? fmax(acc, red[i][k]) : acc + red[i][k];
+        part[k] = acc;
+    }
+}
+
+__global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const double* __restrict__ f,
+                                                              double* __restrict__ partials)
+{
+    const long long n = (long long)K.nx * K.ny;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long s = (long long)blockIdx.x * DIAG_BLOCK + threadIdx.x; s < n; s += (long long)gridDim.x * DIAG_BLOCK) {
+        const int x = (int)(s % K.nx), y = (int)(s / K.nx);
+        double fh[10], d[14], u, v, P;
+        load10(K, f, nidx(K, x, y), fh);
+        node_moments(fh, K.c, u, v, P);
+        derived_node(K, fh, d);
+        const double dA = 1.0 / (K.gx[x] * K.gy[y]);
+        acc[0] += u;
+        acc[1] += v;
+        acc[2] += 0.5 * (u * u + v * v) * dA;
+        acc[3] += 0.5 * d[12] * d[12] * dA;
+        acc[4] = fmax(acc[4], sqrt(u * u + v * v));
+        if (!is_wall(K, x, y)) {
+            const int xp = x + 1 == K.nx ? 0 : x + 1, xm = x == 0 ? K.nx - 1 : x - 1;
+            const int yp = y + 1 == K.ny ? 0 : y + 1, ym = y == 0 ? K.ny - 1 : y - 1;
+            double a[10], b[10], t0, t1, t2, ue, uw, vn, vs;
+            load10(K, f, nidx(K, xp, y), a);
+            node_moments(a, K.c, ue, t1, t2);
+            load10(K, f, nidx(K, xm, y), b);
+            node_moments(b, K.c, uw, t1, t2);
+            load10(K, f, nidx(K, x, yp), a);
+            node_moments(a, K.c, t0, vn, t2);
+            load10(K, f, nidx(K, x, ym), b);
+            node_moments(b, K.c, t0, vs, t2);
+            const double div = (ue - uw) * K.gx[x] * 0.5 + (vn - vs) * K.gy[y] * 0.5;
+            acc[5] = fmax(acc[5], fabs(div));
+        }
+        int bad = 0;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) bad += isfinite(fh[k]) ? 0 : 1;
+        acc[6] += (double)bad;
+        acc[7] += dA;
+    }
+    block_reduce8(acc, partials + 8 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(DIAG_BLOCK) void k_diag_final(const double* __restrict__ partials, int nblocks,
+                                                            double* __restrict__ out)
+{
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += DIAG_BLOCK) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double v = partials[8 * b + k];
+            acc[k] = (k == 4 || k == 5) ? fmax(acc[k], v) : acc[k] + v;
+        }
+    }
+    block_reduce8(acc, out);
+}
+
+// copy between the pitched state and a dense 10 x ny x nx array
+__global__ void k_pack(StepConsts K, const double* __restrict__ f, double* __restrict__ dense)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    const long long n = (long long)K.nx * K.ny, s = (long long)y * K.nx + x;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) dense[k * n + s] = f[k * K.plane + nidx(K, x, y)];
+}
+
+__global__ void k_unpack(StepConsts K, const double* __restrict__ dense, double* __restrict__ f)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    const long long n = (long long)K.nx * K.ny, s = (long long)y * K.nx + x;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) f[k * K.plane + nidx(K, x, y)] = dense[k * n + s];
+}
+
+// ---- three-pass reference step ----
+
+// pass A: f_bar^+ at every node (Step (1), eq. 2.2.15); wall nodes by the wall rule
+__global__ void k_pass_a(StepConsts K, const double* __restrict__ fh, double* __restrict__ fbp)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    int x1, y1, x2, y2;
+    double uw, a[10], out[10];
+    if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
+        double b[10], p1[10], p2[10];
+        load10(K, fh, nidx(K, x1, y1), a);
+        collide1_bar(K, a, p1);
+        load10(K, fh, nidx(K, x2, y2), b);
+        collide1_bar(K, b, p2);
+        wall_extrapolate(K, p1, p2, uw, out);
+    } else {
+        load10(K, fh, nidx(K, x, y), a);
+        collide1_bar(K, a, out);
+    }
+    store10(K, fbp, nidx(K, x, y), out);
+}
+
+// f(t+h) at an interior node: half step (eq. 2.3.25 in Taylor form) then Step (3)
+__device__ __forceinline__ void mid_at(const StepConsts& K, const double* fbp, int x, int y, double* f)
+{
+    double fb[10];
+    const long long i = nidx(K, x, y);
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+        fb[k] = fbp[k * K.plane + i] - transport_at(K, fbp, k, x, y, K.lam_h) + K.hwf[k / 5];
+    collide3(K, fb, f);
+}
+
+__global__ void k_pass_b(StepConsts K, const double* __restrict__ fbp, double* __restrict__ fmid)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    int x1, y1, x2, y2;
+    double uw, out[10];
+    if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
+        double p1[10], p2[10];
+        mid_at(K, fbp, x1, y1, p1);
+        mid_at(K, fbp, x2, y2, p2);
+        wall_extrapolate(K, p1, p2, uw, out);
+    } else {
+        mid_at(K, fbp, x, y, out);
+    }
+    store10(K, fmid, nidx(K, x, y), out);
+}
+
+// f_hat(t+dt) at an interior node: Step (4), eq. 2.3.24
+__device__ __forceinline__ void full_at(const StepConsts& K, const double* fh, const double* fmid, int x, int y,
+                                        double* out)
+{
+    double a[10], fhp[10];
+    load10(K, fh, nidx(K, x, y), a);
+    collide1_hat(K, a, fhp);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[k] = fhp[k] - transport_at(K, fmid, k, x, y, K.lam_dt) + K.dwf[k / 5];
+}
+
+__global__ void k_pass_c(StepConsts K, const double* __restrict__ fh, const double* __restrict__ fmid,
+                         double* __restrict__ fnew)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= K.nx || y >= K.ny) return;
+    int x1, y1, x2, y2;
+    double uw, out[10];
+    if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
+        double p1[10], p2[10];
+        full_at(K, fh, fmid, x1, y1, p1);
+        full_at(K, fh, fmid, x2, y2, p2);
+        wall_extrapolate(K, p1, p2, uw, out);
+    } else {
+        full_at(K, fh, fmid, x, y, out);
+    }
+    store10(K, fnew, nidx(K, x, y), out);
+}
+
+inline dim3 grid2d(const StepConsts& K, dim3 b) { return dim3((K.nx + b.x - 1) / b.x, (K.ny + b.y - 1) / b.y); }
+
+}  // namespace
+
+hipError_t launch_init(const StepConsts& K, const double* u0, const double* v0, const double* p0, double* f,
+                       hipStream_t s)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_init, grid2d(K, b), b, 0, s, K, u0, v0, p0, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_fix(const StepConsts& K, double* f, hipStream_t s)
+{
+    if (!K.bcx && !K.bcy) return hipSuccess;
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_wall_fix, grid2d(K, b), b, 0, s, K, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const StepConsts& K, const double* f, double* u, double* v, double* p, hipStream_t s)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_moments, grid2d(K, b), b, 0, s, K, f, u, v, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_derived(const StepConsts& K, const double* f, double* out, uint32_t mask, hipStream_t s)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_derived, grid2d(K, b), b, 0, s, K, f, out, mask);
+    return hipGetLastError();
+}
+
+int diag_blocks(const StepConsts& K)
+{
+    const long long n = (long long)K.nx * K.ny;
+    long long b = (n + DIAG_BLOCK - 1) / DIAG_BLOCK;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+hipError_t launch_diagnostics(const StepConsts& K, const double* f, double* partials, double* out8, hipStream_t s)
+{
+    const int nb = diag_blocks(K);
+    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(DIAG_BLOCK), 0, s, K, f, partials);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DIAG_BLOCK), 0, s, partials, nb, out8);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const StepConsts& K, const double* f, double* dense, hipStream_t s)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_pack, grid2d(K, b), b, 0, s, K, f, dense);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const StepConsts& K, const double* dense, double* f, hipStream_t s)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_unpack, grid2d(K, b), b, 0, s, K, dense, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew,
+                             hipStream_t s)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_pass_a, grid2d(K, b), b, 0, s, K, fh, fbp);
+    hipLaunchKernelGGL(k_pass_b, grid2d(K, b), b, 0, s, K, fbp, fmid);
+    hipLaunchKernelGGL(k_pass_c, grid2d(K, b), b, 0, s, K, fh, fmid, fnew);
+    return hipGetLastError();
+}
+
+}  // namespace mdf

@@ -1,0 +1,270 @@
+// Device-side building blocks of the MDF-FDLBM step for gfx950.
+//
+// Everything here is per node and register-resident.  The collision is the
+// O(q) closed form of the MRT operator: with rates s_0 = s_3 = s_4 = s' and
+// s_1 = s_2 = s (Sec. 3.1) and an orthogonal moment basis, the constraints of
+// eq. 2.2.4 give Lambda~ = s' I + (s - s') P_c with P_c the projector onto the
+// first moments, (P_c g)_1 = -(P_c g)_3 = (g_1 - g_3)/2 and likewise for 2/4.
+// Any function r(Lambda~) then acts as r(s') g + (r(s) - r(s')) P_c g, so each
+// matrix of Steps (1)-(3) reduces to a pair of scalars per rate:
+//   a(sig) = (1 - sig dt/2)/(1 + sig dt/2)   I - Lambda            (eq. 2.2.14)
+//   b(sig) = (1 + 3 a(sig))/4                I - 3/4 Lambda        (eq. 2.2.15)
+//   q(sig) = 1/(1 + sig dt/4)                (I + h/2 Lambda~)^-1  (eq. 2.2.16)
+// and the mid-step collision (I + h/2 L~)^-1 (f_bar + h/2 L~ f^eq) equals
+// f^eq + R_q(f_bar - f^eq) because the moments of f_bar equal those of f.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mdf {
+
+enum : int { PL_NEWTON = 0, PL_HALF = 1, PL_THREE_HALVES = 2 };
+
+// Constants of one run, computed on the host at mdf_init and passed by value.
+struct StepConsts {
+    int nx, ny;
+    int bcx, bcy;            // 0 periodic, 1 wall
+    int pl;                  // PL_*
+    int pitch;               // doubles per row
+    long long plane;         // doubles per plane
+    double c, w, kf;         // lattice speed, weight 1/5, w c / c_s^2
+    double cs2, dt, h;
+    double eta, one_m_eta;
+    double st_a, st_b, st_c, st_d;   // mixed-difference weights (see transport_pos)
+    double lid_u;
+    // Newtonian relaxation factors for (s, s')
+    double a_s, a_p, b_s, b_p, q_s, q_p;
+    double nu;               // Newtonian viscosity or power-law K
+    double nu_min, nu_max, s_ratio;
+    double theta1, theta3;   // c_s^2 dt/2 and c_s^2 dt/4
+    // transport coefficients: tau * c / 2 for tau = h and tau = dt
+    double lam_h, lam_dt;
+    // body force terms h w F_alpha and dt w F_alpha
+    double hwf[2], dwf[2];
+    const double* gx;        // nx derivative scales 1/(X' dxi)
+    const double* gy;        // ny derivative scales
+};
+
+struct Relax {               // a relaxation pair kappa (rate s), kappa' (rate s')
+    double k, kp;
+};
+
+__device__ __forceinline__ void node_moments(const double* phi, double c, double& u, double& v, double& P)
+{
+    u = ((phi[0] + phi[1]) + (phi[2] + phi[3])) + phi[4];
+    v = ((phi[5] + phi[6]) + (phi[7] + phi[8])) + phi[9];
+    // sum_alpha sum_j c_{j,alpha} phi_{j,alpha}: x-moment of the u set plus y-moment of the v set
+    const double q = c * ((phi[1] - phi[3]) + (phi[7] - phi[9]));
+    P = 0.5 * (q - (u * u + v * v));
+}
+
+// Linear equilibrium of eq. 2.2.5 for both velocity components.
+__device__ __forceinline__ void equilibrium(double u, double v, double P, const StepConsts& K, double* fe)
+{
+    const double fxu = u * u + P, fyu = u * v;   // flux of the u equation
+    const double fxv = v * u, fyv = v * v + P;   // flux of the v equation
+    const double bu = K.w * u, bv = K.w * v;
+    fe[0] = bu;
+    fe[1] = bu + K.kf * fxu;
+    fe[2] = bu + K.kf * fyu;
+    fe[3] = bu - K.kf * fxu;
+    fe[4] = bu - K.kf * fyu;
+    fe[5] = bv;
+    fe[6] = bv + K.kf * fxv;
+    fe[7] = bv + K.kf * fyv;
+    fe[8] = bv - K.kf * fxv;
+    fe[9] = bv - K.kf * fyv;
+}
+
+// out = f^eq + R_{k,k'}(phi - f^eq)
+__device__ __forceinline__ void relax(const double* phi, const double* fe, Relax r, double* out)
+{
+    const double dk = 0.5 * (r.k - r.kp);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const double* p = phi + 5 * a;
+        const double* e = fe + 5 * a;
+        double* o = out + 5 * a;
+        const double g0 = p[0] - e[0], g1 = p[1] - e[1], g2 = p[2] - e[2], g3 = p[3] - e[3], g4 = p[4] - e[4];
+        const double dx = dk * (g1 - g3), dy = dk * (g2 - g4);
+        o[0] = e[0] + r.kp * g0;
+        o[1] = e[1] + (r.kp * g1 + dx);
+        o[3] = e[3] + (r.kp * g3 - dx);
+        o[2] = e[2] + (r.kp * g2 + dy);
+        o[4] = e[4] + (r.kp * g4 - dy);
+    }
+}
+
+// sqrt(2 S^:S^) with S^ = -sym(M^ne), M^ne_{ab} = sum_j c_{j,b} (phi - f^eq)_{j,a}.
+__device__ __forceinline__ double noneq_shear(const double* phi, const double* fe, double c)
+{
+    const double mxx = c * ((phi[1] - fe[1]) - (phi[3] - fe[3]));
+    const double mxy = c * ((phi[2] - fe[2]) - (phi[4] - fe[4]));
+    const double myx = c * ((phi[6] - fe[6]) - (phi[8] - fe[8]));
+    const double myy = c * ((phi[7] - fe[7]) - (phi[9] - fe[9]));
+    const double s12 = 0.5 * (mxy + myx);
+    return sqrt(2.0 * (mxx * mxx + myy * myy + 2.0 * s12 * s12));
+}
+
+// Local power-law viscosity: nu = K (g/(nu + theta))^(n-1), clamped.
+//  n = 1/2: positive root of nu^2 - (K^2/g) nu - K^2 theta/g = 0.
+//  n = 3/2: root of nu^3 + theta nu^2 - K^2 g = 0 by Newton's method from an
+//           upper bound of the root (the cubic is convex and increasing on
+//           nu > 0, so the iterates decrease monotonically to the root).
+__device__ __forceinline__ double powerlaw_nu(const StepConsts& K, double g, double theta)
+{
+    const double Kc = K.nu;
+    double nu;
+    if (K.pl == PL_HALF) {
+        if (g == 0.0) return K.nu_max;
+        const double b = Kc * Kc / g;
+        nu = 0.5 * (b + sqrt(b * b + 4.0 * Kc * Kc * theta / g));
+    } else {
+        if (g == 0.0) return K.nu_min;
+        const double r = Kc * Kc * g;
+        // nu^3 <= r and theta nu^2 <= r bound the root from above
+        double x = cbrt(r);
+        if (theta > 0.0) x = fmin(x, sqrt(r / theta));
+        x = fmin(x * (1.0 + 1e-12), K.nu_max * 2.0);
+        if (K.nu_max * K.nu_max * (K.nu_max + theta) <= r) return K.nu_max;
+        for (int it = 0; it < 60; ++it) {
+            const double f = x * x * (x + theta) - r;
+            const double df = x * (3.0 * x + 2.0 * theta);
+            const double nx = x - f / df;
+            if (!(nx < x)) break;     // converged: Newton stopped decreasing
+            x = nx;
+            if (x <= K.nu_min) break;
+        }
+        nu = x;
+    }
+    return fmin(fmax(nu, K.nu_min), K.nu_max);
+}
+
+__device__ __forceinline__ double relax_a(double sig, double dt) { return (1.0 - 0.5 * sig * dt) / (1.0 + 0.5 * sig * dt); }
+
+// Step (1) factors for a node: a(s), a(s') (f_hat^+) and b(s), b(s') (f_bar^+).
+template <int PL>
+__device__ __forceinline__ void step1_factors_t(const StepConsts& K, const double* fh, const double* fe, Relax& ra,
+                                                Relax& rb)
+{
+    if (PL == PL_NEWTON) {
+        ra = Relax{K.a_s, K.a_p};
+        rb = Relax{K.b_s, K.b_p};
+        return;
+    }
+    const double nu = powerlaw_nu(K, noneq_shear(fh, fe, K.c), K.theta1);
+    const double s = K.cs2 / nu, sp = K.s_ratio * s;
+    const double as = relax_a(s, K.dt), ap = relax_a(sp, K.dt);
+    ra = Relax{as, ap};
+    rb = Relax{0.25 * (1.0 + 3.0 * as), 0.25 * (1.0 + 3.0 * ap)};
+}
+
+// Step (3) factors q(s), q(s') for the collision of f_bar.
+template <int PL>
+__device__ __forceinline__ Relax step3_factors_t(const StepConsts& K, const double* fb, const double* fe)
+{
+    if (PL == PL_NEWTON) return Relax{K.q_s, K.q_p};
+    const double nu = powerlaw_nu(K, noneq_shear(fb, fe, K.c), K.theta3);
+    const double s = K.cs2 / nu, sp = K.s_ratio * s;
+    return Relax{1.0 / (1.0 + 0.25 * s * K.dt), 1.0 / (1.0 + 0.25 * sp * K.dt)};
+}
+
+__device__ __forceinline__ void step1_factors(const StepConsts& K, const double* fh, const double* fe, Relax& ra,
+                                              Relax& rb)
+{
+    if (K.pl == PL_NEWTON)
+        step1_factors_t<PL_NEWTON>(K, fh, fe, ra, rb);
+    else
+        step1_factors_t<PL_HALF>(K, fh, fe, ra, rb);   // both power-law indices share the code path
+}
+
+__device__ __forceinline__ Relax step3_factors(const StepConsts& K, const double* fb, const double* fe)
+{
+    if (K.pl == PL_NEWTON) return step3_factors_t<PL_NEWTON>(K, fb, fe);
+    return step3_factors_t<PL_HALF>(K, fb, fe);
+}
+
+// Step (1): f_hat -> f_hat^+ (eq. 2.2.14) and f_bar^+ (eq. 2.2.15).
+__device__ __forceinline__ void collide1(const StepConsts& K, const double* fh, double* fhp, double* fbp)
+{
+    double u, v, P, fe[10];
+    node_moments(fh, K.c, u, v, P);
+    equilibrium(u, v, P, K, fe);
+    Relax ra, rb;
+    step1_factors(K, fh, fe, ra, rb);
+    relax(fh, fe, ra, fhp);
+    relax(fh, fe, rb, fbp);
+}
+
+__device__ __forceinline__ void collide1_bar(const StepConsts& K, const double* fh, double* fbp)
+{
+    double u, v, P, fe[10];
+    node_moments(fh, K.c, u, v, P);
+    equilibrium(u, v, P, K, fe);
+    Relax ra, rb;
+    step1_factors(K, fh, fe, ra, rb);
+    relax(fh, fe, rb, fbp);
+}
+
+__device__ __forceinline__ void collide1_hat(const StepConsts& K, const double* fh, double* fhp)
+{
+    double u, v, P, fe[10];
+    node_moments(fh, K.c, u, v, P);
+    equilibrium(u, v, P, K, fe);
+    Relax ra, rb;
+    step1_factors(K, fh, fe, ra, rb);
+    relax(fh, fe, ra, fhp);
+}
+
+// Step (3): f(t+h) = f^eq + R_q(f_bar - f^eq) (eq. 2.2.16).
+__device__ __forceinline__ void collide3(const StepConsts& K, const double* fb, double* f)
+{
+    double u, v, P, fe[10];
+    node_moments(fb, K.c, u, v, P);
+    equilibrium(u, v, P, K, fe);
+    const Relax rq = step3_factors(K, fb, fe);
+    relax(fb, fe, rq, f);
+}
+
+// Wall rule: Pi(w) = f^eq(u_w, P_1) + 2 [Pi(1) - f^eq(1)] - [Pi(2) - f^eq(2)]
+// for the components listed in `mask` (bit k = plane k).
+__device__ __forceinline__ void wall_extrapolate(const StepConsts& K, const double* p1, const double* p2, double uw,
+                                                 double* out)
+{
+    double u1, v1, P1, u2, v2, P2, e1[10], e2[10], ew[10];
+    node_moments(p1, K.c, u1, v1, P1);
+    node_moments(p2, K.c, u2, v2, P2);
+    equilibrium(u1, v1, P1, K, e1);
+    equilibrium(u2, v2, P2, K, e2);
+    equilibrium(uw, 0.0, P1, K, ew);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[k] = ew[k] + 2.0 * (p1[k] - e1[k]) - (p2[k] - e2[k]);
+}
+
+// tau c_j . grad Pi for the velocity of sign sg along one axis with the mixed
+// scheme; lam = tau c / 2 and g = 1/(X' dxi) at the node, lamg = lam g.
+//   c > 0: lamg [eta (P1 - Pm1) + (1-eta)(3 P0 - 4 Pm1 + Pm2)]
+//   c < 0: -lamg [eta (P1 - Pm1) - (1-eta)(3 P0 - 4 P1 + P2)]
+// written as four-point weighted sums with w_a = 1-eta, w_b = -(4-3 eta),
+// w_c = 3(1-eta), w_d = eta (the c < 0 branch is the mirror image).
+__device__ __forceinline__ double transport_pos(const StepConsts& K, double lamg, double pm2, double pm1, double p0,
+                                                double p1)
+{
+    return lamg * (K.st_a * pm2 + K.st_b * pm1 + K.st_c * p0 + K.st_d * p1);
+}
+
+__device__ __forceinline__ double transport_neg(const StepConsts& K, double lamg, double pm1, double p0, double p1,
+                                                double p2)
+{
+    return lamg * (K.st_d * pm1 + K.st_c * p0 + K.st_b * p1 + K.st_a * p2);
+}
+
+__device__ __forceinline__ double ghost(double p0, double p1, double p2) { return 3.0 * p0 - 3.0 * p1 + p2; }
+
+__device__ __forceinline__ bool is_wall(const StepConsts& K, int x, int y)
+{
+    return (K.bcx && (x == 0 || x == K.nx - 1)) || (K.bcy && (y == 0 || y == K.ny - 1));
+}
+
+}  // namespace mdf

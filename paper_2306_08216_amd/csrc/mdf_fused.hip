@@ -1,0 +1,432 @@
+// Fused single-pass MDF-FDLBM time step for gfx950.
+//
+// One workgroup owns a column strip of TW lanes (one column per lane; the 4
+// columns at each side are halo) and marches up the rows of one segment.  For
+// the row k entering the march it runs, in registers:
+//   A   load f_hat(k); Step (1) collision -> f_hat^+(k), f_bar^+(k)   (eqs. 2.2.14-15)
+//   A'  x-neighbours of f_bar^+ through LDS; x part of the half step of row k
+//   B   y part of the half step of row m = k-2 from a 4-row register window,
+//       Step (3) collision -> f(t+h)(m)                              (eqs. 2.3.25, 2.2.16)
+//   B'  x-neighbours of f(t+h) through LDS; x part of Step (4) for row m -> store
+//   C   y part of Step (4) for row r = k-4 from the f(t+h) window -> store (eq. 2.3.24)
+// so HBM sees one read and one write of the 10 distribution planes per node.
+// Row windows are 4-deep register rings indexed by (row - first row) & 3; the
+// march is unrolled by 4 so every ring index is a compile-time constant.
+//
+// Walls: the wall rule (non-equilibrium extrapolation from the two inward
+// neighbours) is applied to f_bar^+ and to f(t+h) inside the march; wall nodes
+// of f_hat(t+dt) are not written here -- the stored wall values never enter
+// the next step, and the host applies the rule to the final state once per
+// mdf_step call.  Beyond a wall the stencil uses the quadratic ghost node.
+#include <type_traits>
+
+#include "mdf_device.hpp"
+#include "mdf_internal.hpp"
+
+namespace mdf {
+
+namespace {
+
+struct FusedGrid {
+    int nstrips, nsegs, chunk;
+};
+
+// equilibrium component (velocity along the wall normal axis) used by the wall
+// rule; `ax` is the axis of c_j (0 = x, 1 = y), sg the sign of c_j.
+__device__ __forceinline__ double feq_comp(const StepConsts& K, int a, int ax, double sg, double u, double v, double P)
+{
+    const double ua = a == 0 ? u : v;
+    const double flux = ax == 0 ? (a == 0 ? u * u + P : v * u) : (a == 0 ? u * v : v * v + P);
+    return K.w * ua + sg * K.kf * flux;
+}
+
+// wall value of one component from the inward neighbours n1, n2 (moments m1, m2)
+__device__ __forceinline__ double wall_comp(const StepConsts& K, int a, int ax, double sg, double p1, double p2,
+                                            const double* m1, const double* m2, double uw)
+{
+    const double e1 = feq_comp(K, a, ax, sg, m1[0], m1[1], m1[2]);
+    const double e2 = feq_comp(K, a, ax, sg, m2[0], m2[1], m2[2]);
+    const double ew = feq_comp(K, a, ax, sg, uw, 0.0, m1[2]);
+    return ew + 2.0 * (p1 - e1) - (p2 - e2);
+}
+
+template <int TW>
+__device__ __forceinline__ int lclamp(int l)
+{
+    return l < 0 ? 0 : (l >= TW ? TW - 1 : l);
+}
+
+// Read the x-neighbours (offsets -2..2) of the 4 exchanged components; at
+// x-walls replace the wall column by the wall rule and the column beyond it
+// by the ghost node.  comp c = (alpha = c/2, j = 1 if c even else 3).
+template <int TW, bool WX>
+__device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW], int lane, int x, double nb[4][5],
+                                             double lid)
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int d = -2; d <= 2; ++d) nb[c][d + 2] = X[c][lclamp<TW>(lane + d)];
+    if (WX) {
+        if (x >= 1 && x <= 2) {
+            const int l1 = lclamp<TW>(lane + (1 - x)), l2 = lclamp<TW>(lane + (2 - x));
+            const double m1[3] = {X[4][l1], X[5][l1], X[6][l1]};
+            const double m2[3] = {X[4][l2], X[5][l2], X[6][l2]};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double w0 = wall_comp(K, c >> 1, 0, (c & 1) ? -1.0 : 1.0, X[c][l1], X[c][l2], m1, m2, 0.0);
+                if (x == 1) {
+                    nb[c][1] = w0;
+                    nb[c][0] = ghost(w0, X[c][l1], X[c][l2]);
+                } else {
+                    nb[c][0] = w0;
+                }
+            }
+        }
+        if (x >= K.nx - 3 && x <= K.nx - 2) {
+            const int l1 = lclamp<TW>(lane + (K.nx - 2 - x)), l2 = lclamp<TW>(lane + (K.nx - 3 - x));
+            const double m1[3] = {X[4][l1], X[5][l1], X[6][l1]};
+            const double m2[3] = {X[4][l2], X[5][l2], X[6][l2]};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double w0 = wall_comp(K, c >> 1, 0, (c & 1) ? -1.0 : 1.0, X[c][l1], X[c][l2], m1, m2, 0.0);
+                if (x == K.nx - 2) {
+                    nb[c][3] = w0;
+                    nb[c][4] = ghost(w0, X[c][l1], X[c][l2]);
+                } else {
+                    nb[c][4] = w0;
+                }
+            }
+        }
+    }
+    (void)lid;
+}
+
+template <int TW, bool WX, bool WY, bool PLW>
+__global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __restrict__ fin, double* __restrict__ fout,
+                                              FusedGrid G)
+{
+    __shared__ double xs[2][7][TW];
+
+    // XCD-aware order: consecutive segments of a strip land on the same XCD
+    const int L = (int)(blockIdx.x % 8) * G.chunk + (int)(blockIdx.x / 8);
+    if (L >= G.nstrips * G.nsegs) return;
+    const int strip = L / G.nsegs, seg = L - strip * G.nsegs;
+    const int xs0 = (int)((long long)strip * K.nx / G.nstrips);
+    const int xs1 = (int)((long long)(strip + 1) * K.nx / G.nstrips);
+    const int ys0 = (int)((long long)seg * K.ny / G.nsegs);
+    const int ys1 = (int)((long long)(seg + 1) * K.ny / G.nsegs);
+
+    const int lane = threadIdx.x;
+    const int x = xs0 - 4 + lane;
+    int xg;
+    if (WX) {
+        xg = x < 0 ? 0 : (x >= K.nx ? K.nx - 1 : x);
+    } else {
+        xg = x % K.nx;
+        if (xg < 0) xg += K.nx;
+    }
+    const bool outc = (x >= xs0) && (x < xs1) && (!WX || (x >= 1 && x <= K.nx - 2));
+    const double gxl = K.gx[xg];
+    const double lhx = K.lam_h * gxl, ldx = K.lam_dt * gxl;
+    const long long pl = K.plane;
+
+    auto wrap_y = [&](int k) -> int {
+        if (WY) return k;
+        return k < 0 ? k + K.ny : (k >= K.ny ? k - K.ny : k);
+    };
+    auto row_ok = [&](int k) -> bool { return WY ? (k >= 0 && k < K.ny) : true; };
+
+    const int kbeg = ys0 - 4, kend = ys1 + 3;
+
+    double nxt[10];
+    auto load_row = [&](int k, double* dst) {
+        if (row_ok(k)) {
+            const double* p = fin + (long long)wrap_y(k) * K.pitch + xg;
+#pragma unroll
+            for (int q = 0; q < 10; ++q) dst[q] = p[q * pl];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 10; ++q) dst[q] = 0.0;
+        }
+    };
+
+    double W2[4][2], W4[4][2], F2[4][2], F4[4][2], Qy[4][4], Qx[2][6], Qb[2][6];
+    double ub_prev[3] = {0, 0, 0}, uf_prev[3] = {0, 0, 0}, pend_b[4] = {0, 0, 0, 0}, pend_f[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        W2[i][0] = W2[i][1] = W4[i][0] = W4[i][1] = 0.0;
+        F2[i][0] = F2[i][1] = F4[i][0] = F4[i][1] = 0.0;
+        Qy[i][0] = Qy[i][1] = Qy[i][2] = Qy[i][3] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) Qx[i][q] = Qb[i][q] = 0.0;
+
+    load_row(kbeg, nxt);
+
+    auto body = [&](auto PC, int k) {
+        constexpr int P = decltype(PC)::value;
+        constexpr int S1 = (P + 3) & 3, S2 = (P + 2) & 3, S3 = (P + 1) & 3;   // rows k-1, k-2, k-3
+        double cur[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) cur[q] = nxt[q];
+        if (k + 1 <= kend) load_row(k + 1, nxt);
+
+        // ---- A: Step (1) on row k ----
+        double fbp[10], fhp[10], ub[3];
+        {
+            double fe[10];
+            node_moments(cur, K.c, ub[0], ub[1], ub[2]);
+            equilibrium(ub[0], ub[1], ub[2], K, fe);
+            Relax ra, rb;
+            step1_factors_t<PLW ? PL_HALF : PL_NEWTON>(K, cur, fe, ra, rb);
+            relax(cur, fe, rb, fbp);
+            if (k >= ys0 && k < ys1) {
+                relax(cur, fe, ra, fhp);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 10; ++q) fhp[q] = 0.0;
+            }
+        }
+        double b2[2] = {fbp[2], fbp[7]};
+        W4[P][0] = fbp[4];
+        W4[P][1] = fbp[9];
+        if (WY) {
+            if (k == 2) {   // bottom wall row 0 from rows 1 and 2
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    W2[S2][a] = wall_comp(K, a, 1, 1.0, W2[S1][a], b2[a], ub_prev, ub, 0.0);
+                    W4[S2][a] = wall_comp(K, a, 1, -1.0, W4[S1][a], W4[P][a], ub_prev, ub, 0.0);
+                }
+            }
+            if (k == K.ny - 2) {   // top wall row ny-1 from rows ny-2 and ny-3, used next row
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    pend_b[2 * a] = wall_comp(K, a, 1, 1.0, b2[a], W2[S1][a], ub, ub_prev, K.lid_u);
+                    pend_b[2 * a + 1] = wall_comp(K, a, 1, -1.0, W4[P][a], W4[S1][a], ub, ub_prev, K.lid_u);
+                }
+            }
+            if (k == K.ny - 1) {
+                b2[0] = pend_b[0];
+                b2[1] = pend_b[2];
+                W4[P][0] = pend_b[1];
+                W4[P][1] = pend_b[3];
+            }
+        }
+
+        // ---- A': x part of the half step for row k ----
+        double bx[6];
+        {
+            double(*X)[TW] = xs[0];
+            X[0][lane] = fbp[1];
+            X[1][lane] = fbp[3];
+            X[2][lane] = fbp[6];
+            X[3][lane] = fbp[8];
+            if (WX) {
+                X[4][lane] = ub[0];
+                X[5][lane] = ub[1];
+                X[6][lane] = ub[2];
+            }
+            __syncthreads();
+            double nb[4][5];
+            x_neighbours<TW, WX>(K, X, lane, x, nb, 0.0);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                bx[3 * a + 0] = fbp[5 * a] + K.hwf[a];
+                bx[3 * a + 1] = fbp[5 * a + 1] -
+                                transport_pos(K, lhx, nb[2 * a][0], nb[2 * a][1], nb[2 * a][2], nb[2 * a][3]) + K.hwf[a];
+                bx[3 * a + 2] = fbp[5 * a + 3] -
+                                transport_neg(K, lhx, nb[2 * a + 1][1], nb[2 * a + 1][2], nb[2 * a + 1][3],
+                                              nb[2 * a + 1][4]) + K.hwf[a];
+            }
+        }
+
+        // ---- B: half step (y part) and Step (3) on row m = k-2 ----
+        const int m = k - 2;
+        const bool needB = (m >= ys0 - 2) && (m < ys1 + 2) && (WY ? (m >= 1 && m <= K.ny - 2) : true);
+        double f2c[2] = {0.0, 0.0};
+        double fm[10], uf[3] = {0.0, 0.0, 0.0};
+        if (needB) {
+            const double lhy = K.lam_h * K.gy[wrap_y(m)];
+            double fb[10];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                double a2[4] = {W2[P][a], W2[S3][a], W2[S2][a], W2[S1][a]};   // rows m-2 .. m+1
+                double a4[4] = {W4[S3][a], W4[S2][a], W4[S1][a], W4[P][a]};   // rows m-1 .. m+2
+                if (WY && m == 1) a2[0] = ghost(a2[1], a2[2], a2[3]);
+                if (WY && m == K.ny - 2) a4[3] = ghost(a4[2], a4[1], a4[0]);
+                fb[5 * a + 0] = Qb[P & 1][3 * a + 0];
+                fb[5 * a + 1] = Qb[P & 1][3 * a + 1];
+                fb[5 * a + 3] = Qb[P & 1][3 * a + 2];
+                fb[5 * a + 2] = a2[2] - transport_pos(K, lhy, a2[0], a2[1], a2[2], a2[3]) + K.hwf[a];
+                fb[5 * a + 4] = a4[1] - transport_neg(K, lhy, a4[0], a4[1], a4[2], a4[3]) + K.hwf[a];
+            }
+            double fe[10];
+            node_moments(fb, K.c, uf[0], uf[1], uf[2]);
+            equilibrium(uf[0], uf[1], uf[2], K, fe);
+            const Relax rq = step3_factors_t<PLW ? PL_HALF : PL_NEWTON>(K, fb, fe);
+            relax(fb, fe, rq, fm);
+            F4[S2][0] = fm[4];
+            F4[S2][1] = fm[9];
+            f2c[0] = fm[2];
+            f2c[1] = fm[7];
+        }
+        if (WY) {
+            if (m == 2) {   // bottom wall row 0 of f(t+h)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    F2[P][a] = wall_comp(K, a, 1, 1.0, F2[S3][a], f2c[a], uf_prev, uf, 0.0);
+                    F4[P][a] = wall_comp(K, a, 1, -1.0, F4[S3][a], F4[S2][a], uf_prev, uf, 0.0);
+                }
+            }
+            if (m == K.ny - 2) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    pend_f[2 * a] = wall_comp(K, a, 1, 1.0, f2c[a], F2[S3][a], uf, uf_prev, K.lid_u);
+                    pend_f[2 * a + 1] = wall_comp(K, a, 1, -1.0, F4[S2][a], F4[S3][a], uf, uf_prev, K.lid_u);
+                }
+            }
+            if (m == K.ny - 1) {
+                f2c[0] = pend_f[0];
+                f2c[1] = pend_f[2];
+                F4[S2][0] = pend_f[1];
+                F4[S2][1] = pend_f[3];
+            }
+        }
+
+        // ---- B': x part of Step (4) on row m ----
+        const bool outm = needB && (m >= ys0) && (m < ys1);
+        if (outm) {
+            double(*X)[TW] = xs[1];
+            X[0][lane] = fm[1];
+            X[1][lane] = fm[3];
+            X[2][lane] = fm[6];
+            X[3][lane] = fm[8];
+            if (WX) {
+                X[4][lane] = uf[0];
+                X[5][lane] = uf[1];
+                X[6][lane] = uf[2];
+            }
+            __syncthreads();
+            double nb[4][5];
+            x_neighbours<TW, WX>(K, X, lane, x, nb, 0.0);
+            if (outc) {
+                double* o = fout + (long long)wrap_y(m) * K.pitch + xg;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const double h0 = Qx[P & 1][3 * a + 0] + K.dwf[a];
+                    const double h1 = Qx[P & 1][3 * a + 1] -
+                                      transport_pos(K, ldx, nb[2 * a][0], nb[2 * a][1], nb[2 * a][2], nb[2 * a][3]) +
+                                      K.dwf[a];
+                    const double h3 = Qx[P & 1][3 * a + 2] -
+                                      transport_neg(K, ldx, nb[2 * a + 1][1], nb[2 * a + 1][2], nb[2 * a + 1][3],
+                                                    nb[2 * a + 1][4]) + K.dwf[a];
+                    o[(5 * a + 0) * pl] = h0;
+                    o[(5 * a + 1) * pl] = h1;
+                    o[(5 * a + 3) * pl] = h3;
+                }
+            }
+        } else {
+            __syncthreads();   // keeps the two LDS buffers strictly alternating
+        }
+
+        // ---- C: y part of Step (4) on row r = k-4 ----
+        const int r = k - 4;
+        const bool outr = (r >= ys0) && (r < ys1) && (WY ? (r >= 1 && r <= K.ny - 2) : true);
+        if (outr && outc) {
+            const double ldy = K.lam_dt * K.gy[wrap_y(r)];
+            double* o = fout + (long long)wrap_y(r) * K.pitch + xg;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                double c2[4] = {F2[S2][a], F2[S1][a], F2[P][a], F2[S3][a]};   // rows r-2 .. r+1
+                double c4[4] = {F4[S1][a], F4[P][a], F4[S3][a], F4[S2][a]};   // rows r-1 .. r+2
+                if (WY && r == 1) c2[0] = ghost(c2[1], c2[2], c2[3]);
+                if (WY && r == K.ny - 2) c4[3] = ghost(c4[2], c4[1], c4[0]);
+                const double h2 = Qy[P][2 * a] - transport_pos(K, ldy, c2[0], c2[1], c2[2], c2[3]) + K.dwf[a];
+                const double h4 = Qy[P][2 * a + 1] - transport_neg(K, ldy, c4[0], c4[1], c4[2], c4[3]) + K.dwf[a];
+                o[(5 * a + 2) * pl] = h2;
+                o[(5 * a + 4) * pl] = h4;
+            }
+        }
+
+        // ---- ring pushes ----
+        W2[P][0] = b2[0];
+        W2[P][1] = b2[1];
+        Qy[P][0] = fhp[2];
+        Qy[P][1] = fhp[4];
+        Qy[P][2] = fhp[7];
+        Qy[P][3] = fhp[9];
+        Qx[P & 1][0] = fhp[0];
+        Qx[P & 1][1] = fhp[1];
+        Qx[P & 1][2] = fhp[3];
+        Qx[P & 1][3] = fhp[5];
+        Qx[P & 1][4] = fhp[6];
+        Qx[P & 1][5] = fhp[8];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) Qb[P & 1][q] = bx[q];
+        F2[S2][0] = f2c[0];
+        F2[S2][1] = f2c[1];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            ub_prev[q] = ub[q];
+            if (needB) uf_prev[q] = uf[q];
+        }
+    };
+
+    for (int k = kbeg; k <= kend; k += 4) {
+        body(std::integral_constant<int, 0>{}, k);
+        if (k + 1 <= kend) body(std::integral_constant<int, 1>{}, k + 1);
+        if (k + 2 <= kend) body(std::integral_constant<int, 2>{}, k + 2);
+        if (k + 3 <= kend) body(std::integral_constant<int, 3>{}, k + 3);
+    }
+}
+
+template <int TW, bool PLW>
+hipError_t launch_tw(const StepConsts& K, const FusedGrid& G, const double* fin, double* fout, hipStream_t s)
+{
+    const dim3 grid(G.chunk * 8), block(TW);
+    if (K.bcx && K.bcy)
+        hipLaunchKernelGGL((k_fused<TW, true, true, PLW>), grid, block, 0, s, K, fin, fout, G);
+    else if (K.bcx)
+        hipLaunchKernelGGL((k_fused<TW, true, false, PLW>), grid, block, 0, s, K, fin, fout, G);
+    else if (K.bcy)
+        hipLaunchKernelGGL((k_fused<TW, false, true, PLW>), grid, block, 0, s, K, fin, fout, G);
+    else
+        hipLaunchKernelGGL((k_fused<TW, false, false, PLW>), grid, block, 0, s, K, fin, fout, G);
+    return hipGetLastError();
+}
+
+template <int TW>
+hipError_t launch_pl(const StepConsts& K, const FusedGrid& G, const double* fin, double* fout, hipStream_t s)
+{
+    if (K.pl == PL_NEWTON) return launch_tw<TW, false>(K, G, fin, fout, s);
+    return launch_tw<TW, true>(K, G, fin, fout, s);
+}
+
+}  // namespace
+
+bool fused_shape_ok(const StepConsts& K, FusedShape sh)
+{
+    (void)K;
+    return (sh.tile_w == 64 || sh.tile_w == 128 || sh.tile_w == 256) && sh.seg_h >= 1;
+}
+
+hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s)
+{
+    FusedGrid G;
+    const int wout = sh.tile_w - 8;
+    G.nstrips = (K.nx + wout - 1) / wout;
+    G.nsegs = (K.ny + sh.seg_h - 1) / sh.seg_h;
+    const int total = G.nstrips * G.nsegs;
+    G.chunk = (total + 7) / 8;
+    switch (sh.tile_w) {
+    case 64: return launch_pl<64>(K, G, fin, fout, s);
+    case 128: return launch_pl<128>(K, G, fin, fout, s);
+    case 256: return launch_pl<256>(K, G, fin, fout, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mdf

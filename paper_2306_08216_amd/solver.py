@@ -1,0 +1,115 @@
+"""Solver: one MDF-FDLBM run on the GPU through the C ABI.
+
+PyTorch provides the device memory (workspace, field tensors) and the stream;
+all arithmetic runs in the HIP kernels of libmdf.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .problems import Problem
+
+DERIVED_NAMES = ["ux", "uy", "vx", "vy", "div", "Sxx", "Sxy", "Syy", "sig_xx", "sig_xy", "sig_yy",
+                 "Omega_xy", "omega", "nu"]
+DIAG_NAMES = ["sum_u", "sum_v", "ke", "enstrophy", "max_speed", "max_fd_div", "nonfinite", "area"]
+
+
+def params_of(prob: Problem, keep: list) -> L.mdf_params:
+    """Marshal a Problem into the C parameter struct (metric arrays stay owned by `keep`)."""
+    def arr(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+    return L.mdf_params(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
+                        prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
+                        prob.fx, prob.fy, arr(prob.inv_dx_x), arr(prob.inv_dx_y), prob.dx_min)
+
+
+class Solver:
+    def __init__(self, prob: Problem, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        L.lib()
+        self.prob = prob
+        self.device = torch.device(device)
+        self.nx, self.ny = prob.nx, prob.ny
+        keep: list = []
+        self._p = params_of(prob, keep)
+        nbytes = L.mdf_workspace_size(self._p)
+        if nbytes == 0:
+            raise L.MdfError(L.MDF_EINVAL, "invalid problem parameters")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(self.stream):
+            u0 = torch.as_tensor(np.ascontiguousarray(prob.u0), dtype=torch.float64).to(self.device)
+            v0 = torch.as_tensor(np.ascontiguousarray(prob.v0), dtype=torch.float64).to(self.device)
+            p0 = torch.as_tensor(np.ascontiguousarray(prob.p0), dtype=torch.float64).to(self.device)
+        self.stream.synchronize()
+        self.ctx = L.mdf_init(self._p, u0.data_ptr(), v0.data_ptr(), p0.data_ptr(), self.workspace.data_ptr(),
+                              nbytes, self.stream.cuda_stream)
+        del keep
+
+    # -- life cycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.mdf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C calls ---------------------------------------------------------
+    @property
+    def dt(self) -> float:
+        return L.mdf_dt(self.ctx)
+
+    @property
+    def steps(self) -> int:
+        return L.mdf_steps(self.ctx)
+
+    def set_kernel(self, variant: int, tile_w: int = 0, seg_h: int = 0):
+        L.mdf_set_kernel(self.ctx, variant, tile_w, seg_h)
+        return self
+
+    def step(self, n: int = 1):
+        L.mdf_step(self.ctx, n)
+        return self
+
+    def moments(self):
+        u = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        v = torch.empty_like(u)
+        p = torch.empty_like(u)
+        L.mdf_moments(self.ctx, u.data_ptr(), v.data_ptr(), p.data_ptr())
+        return u, v, p
+
+    def derived(self, mask: int = (1 << 14) - 1) -> torch.Tensor:
+        k = bin(mask).count("1")
+        out = torch.empty((k, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.mdf_derived(self.ctx, out.data_ptr(), mask)
+        return out
+
+    def diagnostics(self):
+        buf = (C.c_double * 8)()
+        status = L.mdf_diagnostics(self.ctx, buf)
+        return np.array(buf[:]), status
+
+    def save(self) -> torch.Tensor:
+        f = torch.empty((10, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.mdf_save(self.ctx, f.data_ptr())
+        return f
+
+    def load(self, f: torch.Tensor):
+        assert f.dtype == torch.float64 and f.is_contiguous() and tuple(f.shape) == (10, self.ny, self.nx)
+        L.mdf_load(self.ctx, f.data_ptr())
+        return self
+
+    def synchronize(self):
+        self.stream.synchronize()

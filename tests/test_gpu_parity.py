@@ -1,0 +1,286 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element, on the same seeded inputs.  Bar: max |GPU - oracle| <= 1e-12 on
+the FP64 state after the stated number of steps."""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2306_08216_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_08216_amd.solver import Solver
+    return Solver
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_run(key):
+    from oracle.orc import Oracle
+    prob, steps = CASES[key]()
+    o = Oracle(prob)
+    o.step(steps)
+    return o, prob, steps
+
+
+def _wall_field(n, seed=3, amp=0.02):
+    """Smooth velocity field vanishing on the walls of [0,1]^2 (sine modes)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(n) / (n - 1)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u = np.zeros((n, n))
+    v = np.zeros((n, n))
+    for _ in range(6):
+        kx, ky = rng.integers(1, 5, size=2)
+        a, b = rng.normal(size=2) * amp / 3
+        u += a * np.sin(math.pi * kx * X) * np.sin(math.pi * ky * Y)
+        v += b * np.sin(math.pi * ky * X) * np.sin(math.pi * kx * Y)
+    return u, v, np.zeros((n, n))
+
+
+def _wall_problem(n, pl_n=1.0, beta=None):
+    prob = P.cavity(n, re=1000.0) if pl_n == 1.0 else P.powerlaw_cavity(n, pl_n=pl_n)
+    if beta is None and pl_n != 1.0:
+        prob.inv_dx_x = prob.inv_dx_y = None
+        prob.dx_min = 0.0
+    u, v, p = _wall_field(n)
+    prob.u0, prob.v0, prob.p0 = u, v, p
+    return prob
+
+
+def _ragged():
+    u, v, p = P.random_vortex_fields(96, seed=11, kmax=6, urms=0.03)
+    u, v, p = u[:52, :80].copy(), v[:52, :80].copy(), p[:52, :80].copy()
+    return P.Problem(nx=80, ny=52, lx=2 * math.pi * 80 / 96, ly=2 * math.pi * 52 / 96, nu=0.004, u0=u, v0=v, p0=p)
+
+
+def _wallx():
+    prob = P.poiseuille(40, nu=0.01, force=1e-4)
+    prob.bc_x, prob.bc_y = P.WALL, P.PERIODIC
+    prob.fx, prob.fy = 0.0, 1e-4
+    u, v, _ = _wall_field(40, seed=5)
+    prob.u0, prob.v0 = v.T.copy(), u.T.copy()
+    return prob
+
+
+def _mapped():
+    n = 64
+    prob = P.taylor_green(n, nu=0.005)
+    pos, g, dxm = P.sine_mapping(n, 0.2)
+    X, Y = np.meshgrid(pos, pos, indexing="xy")
+    prob.u0 = 0.01 * np.sin(X) * np.cos(Y)
+    prob.v0 = -0.01 * np.cos(X) * np.sin(Y)
+    prob.p0 = 0.25e-4 * (np.cos(2 * X) + np.cos(2 * Y))
+    prob.inv_dx_x, prob.inv_dx_y, prob.dx_min = g, g.copy(), dxm
+    return prob
+
+
+def _plcav(pl_n):
+    prob = P.powerlaw_cavity(64, pl_n=pl_n)
+    u, v, p = _wall_field(64, seed=9, amp=0.05 if pl_n < 1 else 0.02)
+    prob.u0, prob.v0 = u, v
+    if pl_n > 1:
+        # at 64^2 the default ceiling (100 nu_ref) lets nu exceed c*dx at the lid
+        # corners and the run diverges; a lower ceiling keeps the case bounded
+        prob.nu_max = 0.004
+    return prob
+
+
+CASES = {
+    "tg64": lambda: (P.taylor_green(64, u0=0.01, nu=0.01), 1000),
+    "ragged": lambda: (_ragged(), 200),
+    "cavity128": lambda: (P.cavity(128, re=1000.0), 1000),
+    "cavity_field48": lambda: (_wall_problem(48), 300),
+    "poiseuille32": lambda: (P.poiseuille(32, nu=0.01, force=1e-4), 500),
+    "wallx40": lambda: (_wallx(), 300),
+    "mapped64": lambda: (_mapped(), 200),
+    "plcav_n0.5": lambda: (_plcav(0.5), 200),
+    "plcav_n1.5": lambda: (_plcav(1.5), 200),
+}
+
+
+def _run_gpu(Solver, prob, steps, variant, shape=(0, 0)):
+    s = Solver(prob, device="cuda:0")
+    s.set_kernel(variant, *shape)
+    s.step(steps)
+    f = s.save().cpu().numpy()
+    u, v, p = (t.cpu().numpy() for t in s.moments())
+    s.close()
+    return f, u, v, p
+
+
+def _compare(key, Solver, variant, shape=(0, 0)):
+    o, prob, steps = oracle_run(key)
+    say(f"[gpu parity] case={key} nx={prob.nx} ny={prob.ny} steps={steps} variant={variant} shape={shape}")
+    f, u, v, p = _run_gpu(Solver, prob, steps, variant, shape)
+    fo = o.f()
+    uo, vo, po = o.moments()
+    err = np.abs(f - fo).max()
+    say(f"    max|df|={err:.3e} max|f|={np.abs(fo).max():.3e}")
+    assert np.all(np.isfinite(f))
+    assert err <= TOL, (key, err)
+    assert np.abs(u - uo).max() <= TOL and np.abs(v - vo).max() <= TOL and np.abs(p - po).max() <= TOL
+    return o
+
+
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (0, 0)), (1, (64, 8)), (1, (128, 5)), (1, (256, 64))])
+def test_taylor_green_64_1000_steps(gpu, variant, shape):
+    """The 64^2 Taylor-Green configuration: 1000 FP64 steps agree with the oracle to 1e-12."""
+    _compare("tg64", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 7)), (1, (128, 3)), (1, (64, 1))])
+def test_ragged_periodic(gpu, variant, shape):
+    """80 x 52 periodic grid: several strips, a ragged last strip, segments of 1-7 rows."""
+    _compare("ragged", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (0, 0)), (1, (64, 9))])
+def test_cavity_128_1000_steps(gpu, variant, shape):
+    """Lid-driven cavity (the 1024^2 configuration at 128^2): walls on all sides, lid 0.1."""
+    _compare("cavity128", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 5)), (1, (128, 48))])
+def test_cavity_with_interior_field(gpu, variant, shape):
+    _compare("cavity_field48", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 6)), (1, (256, 32))])
+def test_poiseuille_walls_in_y(gpu, variant, shape):
+    _compare("poiseuille32", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 6)), (1, (128, 13))])
+def test_walls_in_x_periodic_y(gpu, variant, shape):
+    _compare("wallx40", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 10))])
+def test_mapped_periodic_grid(gpu, variant, shape):
+    _compare("mapped64", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("pl_n", [0.5, 1.5])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 8))])
+def test_powerlaw_stretched_cavity(gpu, pl_n, variant, shape):
+    """Power-law cavity on the tanh-stretched grid (the 2048^2 configuration at 64^2)."""
+    _compare(f"plcav_n{pl_n}", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("key", ["tg64", "cavity128", "plcav_n0.5", "plcav_n1.5"])
+def test_derived_and_diagnostics(gpu, key):
+    """mdf_derived (eqs. 2.4.1-2.4.5, all 14 planes) and mdf_diagnostics against the oracle."""
+    o, prob, steps = oracle_run(key)
+    say(f"[gpu derived] case={key}")
+    s = gpu(prob, device="cuda:0")
+    s.step(steps)
+    d = s.derived().cpu().numpy()
+    do = o.derived()
+    for k in range(14):
+        scale = max(np.abs(do[k]).max(), 1e-30)
+        err = np.abs(d[k] - do[k]).max()
+        assert err <= 1e-9 * scale + 1e-13, (k, err, scale)
+    # a subset in mask order
+    mask = (1 << 1) | (1 << 6) | (1 << 12)
+    sub = s.derived(mask).cpu().numpy()
+    np.testing.assert_allclose(sub, do[[1, 6, 12]], rtol=1e-9, atol=1e-13)
+    diag, status = s.diagnostics()
+    dio = o.diagnostics()
+    assert status == 0
+    np.testing.assert_allclose(diag[[2, 3, 4, 5, 7]], dio[[2, 3, 4, 5, 7]], rtol=1e-9)
+    assert abs(diag[0] - dio[0]) <= 1e-12 * max(1.0, np.abs(o.moments()[0]).sum())
+    assert abs(diag[1] - dio[1]) <= 1e-12 * max(1.0, np.abs(o.moments()[1]).sum())
+    assert diag[6] == 0.0
+    s.close()
+
+
+def test_save_load_resume_and_determinism(gpu):
+    """n steps + save/load + n steps equals 2n steps bit for bit; two runs are bitwise equal."""
+    import torch
+    prob = P.cavity(96, re=400.0)
+    say("[gpu resume] cavity96")
+    a = gpu(prob, device="cuda:0")
+    a.step(100)
+    snap = a.save().clone()
+    a.step(100)
+    fa = a.save().cpu().numpy()
+    b = gpu(prob, device="cuda:0")
+    b.load(snap)
+    b.step(100)
+    fb = b.save().cpu().numpy()
+    c = gpu(prob, device="cuda:0")
+    c.step(200)
+    fc = c.save().cpu().numpy()
+    assert np.array_equal(fa, fc)
+    assert np.array_equal(fb, fc)
+    assert c.steps == 200 and b.steps == 100
+    for s in (a, b, c):
+        s.close()
+    del torch
+
+
+def test_diagnostics_flags_non_finite_state(gpu):
+    """A non-finite value injected into the loaded state trips MDF_EUNSTABLE."""
+    import torch
+    prob = P.taylor_green(32)
+    s = gpu(prob, device="cuda:0")
+    f = s.save()
+    f[3, 5, 7] = float("nan")
+    s.load(f.contiguous())
+    diag, status = s.diagnostics()
+    assert status == -4 and diag[6] >= 1
+    s.close()
+    del torch
+
+
+def test_full_size_cavity_1024_default_launch(gpu):
+    """The 1024^2 cavity at full size in the default (benchmarked) launch
+    configuration: 3 steps from a smooth interior field, every node against
+    the oracle."""
+    from oracle.orc import Oracle
+    prob = _wall_problem(1024)
+    say("[gpu full-size] cavity 1024^2, 3 steps, default launch")
+    s = gpu(prob, device="cuda:0")
+    s.step(3)
+    f = s.save().cpu().numpy()
+    s.close()
+    o = Oracle(prob)
+    o.step(3)
+    err = np.abs(f - o.f()).max()
+    say(f"    max|df|={err:.3e}")
+    assert err <= TOL
+
+
+def test_full_size_powerlaw_2048_sampled(gpu):
+    """The 2048^2 power-law stretched cavity at full size (n = 0.5): 1 step in the
+    default launch configuration, every node against the oracle."""
+    from oracle.orc import Oracle
+    prob = P.powerlaw_cavity(2048, pl_n=0.5)
+    u, v, p = _wall_field(2048, seed=13, amp=0.05)
+    prob.u0, prob.v0 = u, v
+    say("[gpu full-size] power-law cavity 2048^2 n=0.5, 1 step, default launch")
+    s = gpu(prob, device="cuda:0")
+    s.step(1)
+    f = s.save().cpu().numpy()
+    s.close()
+    o = Oracle(prob)
+    o.step(1)
+    err = np.abs(f - o.f()).max()
+    say(f"    max|df|={err:.3e}")
+    assert err <= TOL
