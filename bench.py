@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--seg-h", type=int, default=0)
     ap.add_argument("--variant", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="after timing, run this many plain state copies (mdf_save: 80 B read + 80 B written "
+                         "per node) as the known-size reference for HBM byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -106,6 +109,11 @@ def main():
     if status != 0:
         log(f"warning: diagnostics status {status}: {diag}")
 
+    if args.copy_calib > 0:
+        for _ in range(args.copy_calib):
+            s.save()
+        torch.cuda.synchronize(dev)
+
     nodes = prob.nodes
     sec = gpu_ms / 1e3
     mlups = nodes * args.steps / sec / 1e6
@@ -139,7 +147,9 @@ def main():
                    "wall_s": round(wall, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

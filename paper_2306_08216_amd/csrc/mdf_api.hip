@@ -156,14 +156,17 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
 
 mdf::FusedShape default_shape(const mdf_params& p)
 {
+    // One wave per strip (64 columns, 56 outputs) and enough row segments for
+    // about 4096 workgroups: the step is latency bound at one wave per SIMD,
+    // so many short segments beat fewer tall ones down to about 8 rows.
     mdf::FusedShape sh;
-    sh.tile_w = p.nx >= 960 ? 256 : (p.nx >= 240 ? 128 : 64);
+    sh.tile_w = 64;
     const int nstrips = (p.nx + sh.tile_w - 9) / (sh.tile_w - 8);
-    // aim at about 1024 workgroups, with segments of at least 8 rows
-    int nseg = 1024 / (nstrips > 0 ? nstrips : 1);
+    int nseg = 4096 / (nstrips > 0 ? nstrips : 1);
     if (nseg < 1) nseg = 1;
     int h = (p.ny + nseg - 1) / nseg;
     if (h < 8) h = 8;
+    if (h > 64) h = 64;
     sh.seg_h = h;
     return sh;
 }
