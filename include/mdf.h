@@ -49,7 +49,7 @@ typedef enum { MDF_BC_PERIODIC = 0, MDF_BC_WALL = 1 } mdf_bc;
 
 /* Problem parameters (Sec. 2 and the set-ups of Sec. 4).  Host memory. */
 typedef struct {
-    int32_t nx, ny;          /* nodes per axis; >= 5 on every axis (wall axes include the wall nodes) */
+    int32_t nx, ny;          /* nodes per axis, 5..32768 (wall axes include the wall nodes)          */
     double  lx, ly;          /* domain lengths                                                     */
     double  nu;              /* kinematic viscosity nu = c_s^2/s (eq. 2.3.14); the consistency K
                                 of the power law when pl_n != 1                                     */
@@ -81,7 +81,8 @@ size_t mdf_workspace_size(const mdf_params* p);
  *   hip_stream hipStream_t the context enqueues on (NULL = default stream)
  *   out        receives the context
  * Synchronises the stream before returning.  Returns MDF_EINVAL when nu <= 0,
- * cfl <= 0, c <= 0, eta outside [0,1], an axis has fewer than 5 nodes, pl_n is
+ * cfl <= 0, c <= 0, eta outside [0,1], an axis has fewer than 5 or more than
+ * 32768 nodes, pl_n is
  * not 1, 0.5 or 1.5, the power-law clamp is empty, metrics come without dx_min,
  * or the workspace is too small or misaligned. */
 mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0,
@@ -118,10 +119,13 @@ mdf_status mdf_save(mdf_ctx* ctx, double* f);
 mdf_status mdf_load(mdf_ctx* ctx, const double* f);
 
 /* Kernel selection for the time step: variant 0 = three-pass reference path,
- * 1 = fused single-pass strip kernel (default).  tile_w (columns per
- * workgroup, incl. the 8-column halo; 64, 128 or 256) and seg_h
- * (rows per segment, >= 1) apply to variant 1; 0 keeps the current value. */
-mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t seg_h);
+ * 1 = fused single-pass strip kernel with one wave per strip, 2 = fused
+ * single-pass strip kernel with one wave per velocity component (default).
+ * tile_w (columns per strip incl. the 8-column halo; 64 or 128; variant 1
+ * only), seg_h (rows per segment, >= 1) and prefetch (rows loaded ahead,
+ * 2 or 3) apply to the fused variants; 0 keeps the current value.  Results
+ * agree to rounding whatever the choice. */
+mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t seg_h, int32_t prefetch);
 
 double      mdf_dt(const mdf_ctx* ctx);          /* time step, or 0 for NULL       */
 int64_t     mdf_steps(const mdf_ctx* ctx);       /* steps taken since mdf_init     */

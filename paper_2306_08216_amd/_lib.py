@@ -45,7 +45,7 @@ SIGNATURES = {
     "mdf_diagnostics": (C.c_int, [C.c_void_p, _dp]),
     "mdf_save": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mdf_load": (C.c_int, [C.c_void_p, C.c_void_p]),
-    "mdf_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "mdf_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "mdf_dt": (C.c_double, [C.c_void_p]),
     "mdf_steps": (C.c_int64, [C.c_void_p]),
     "mdf_last_error": (C.c_char_p, [C.c_void_p]),
@@ -123,8 +123,8 @@ def mdf_load(ctx: int, f: int):
     return check(lib().mdf_load(ctx, f), ctx)
 
 
-def mdf_set_kernel(ctx: int, variant: int, tile_w: int = 0, seg_h: int = 0):
-    return check(lib().mdf_set_kernel(ctx, int(variant), int(tile_w), int(seg_h)), ctx)
+def mdf_set_kernel(ctx: int, variant: int, tile_w: int = 0, seg_h: int = 0, prefetch: int = 0):
+    return check(lib().mdf_set_kernel(ctx, int(variant), int(tile_w), int(seg_h), int(prefetch)), ctx)
 
 
 def mdf_dt(ctx: int) -> float:

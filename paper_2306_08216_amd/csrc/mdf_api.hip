@@ -28,8 +28,8 @@ struct mdf_ctx {
     double* diag_out = nullptr;
     int cur = 0;
     int64_t steps = 0;
-    int variant = 1;
-    mdf::FusedShape shape{256, 32};
+    int variant = 2;
+    mdf::FusedShape shape{64, 8, 2};
     StepConsts K;
     std::string err;
 };
@@ -57,7 +57,7 @@ mdf_status hip_check(mdf_ctx* c, hipError_t e, const char* what)
 }
 
 struct Layout {
-    size_t pitch, plane;          // doubles
+    size_t pitch;                 // nodes per row
     size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, total;  // bytes
 };
 
@@ -66,11 +66,10 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 Layout layout_for(int nx, int ny)
 {
     Layout L;
+    // rows of 80 bytes per node (x-part block, then y-part block); 16-node multiples keep
+    // rows and both blocks 256-byte aligned
     L.pitch = ((size_t)nx + 15) & ~size_t(15);
-    // pad each plane by 512 B and round to 256 B so that the ten planes do not
-    // start at power-of-two strides from each other
-    L.plane = (L.pitch * (size_t)ny + 64 + 31) & ~size_t(31);
-    const size_t fbytes = align256(10 * L.plane * sizeof(double));
+    const size_t fbytes = align256(10 * L.pitch * (size_t)ny * sizeof(double));
     size_t o = 0;
     L.off_f0 = o;   o += fbytes;
     L.off_f1 = o;   o += fbytes;
@@ -88,7 +87,7 @@ const char* validate(const mdf_params* p)
 {
     if (!p) return "params is NULL";
     if (p->nx < 5 || p->ny < 5) return "nx and ny must be >= 5";
-    if ((long long)p->nx * p->ny > (1LL << 31)) return "grid too large (nx*ny > 2^31)";
+    if (p->nx > 32768 || p->ny > 32768) return "nx and ny must be <= 32768";
     if (!(p->lx > 0.0) || !(p->ly > 0.0)) return "lx and ly must be > 0";
     if (!(p->nu > 0.0)) return "nu must be > 0";
     if (!(p->cfl > 0.0)) return "cfl must be > 0";
@@ -114,7 +113,6 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.bcy = p.bc_y;
     K.pl = p.pl_n == 1.0 ? mdf::PL_NEWTON : (p.pl_n == 0.5 ? mdf::PL_HALF : mdf::PL_THREE_HALVES);
     K.pitch = (int)L.pitch;
-    K.plane = (long long)L.plane;
     K.c = p.c;
     K.w = 0.2;                                  // D2Q5 weights 1/5
     K.cs2 = 0.4 * p.c * p.c;                    // sum_j w_j c_jx^2 = 2c^2/5
@@ -147,6 +145,16 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.q_p = 1.0 / (1.0 + 0.25 * sp * K.dt);
     K.lam_h = 0.5 * K.h * p.c;
     K.lam_dt = 0.5 * K.dt * p.c;
+    K.uniform = (p.inv_dx_x == nullptr && p.inv_dx_y == nullptr) ? 1 : 0;
+    {
+        const double g[2] = {1.0 / hx, 1.0 / hy};
+        for (int ax = 0; ax < 2; ++ax) {
+            const mdf::Stencil a = mdf::make_stencil(K, K.lam_h * g[ax], true);
+            const mdf::Stencil b = mdf::make_stencil(K, K.lam_dt * g[ax], false);
+            K.sh[ax][0] = a.a; K.sh[ax][1] = a.b; K.sh[ax][2] = a.c; K.sh[ax][3] = a.d;
+            K.sd[ax][0] = b.a; K.sd[ax][1] = b.b; K.sd[ax][2] = b.c; K.sd[ax][3] = b.d;
+        }
+    }
     K.hwf[0] = K.h * K.w * p.fx;
     K.hwf[1] = K.h * K.w * p.fy;
     K.dwf[0] = K.dt * K.w * p.fx;
@@ -161,6 +169,7 @@ mdf::FusedShape default_shape(const mdf_params& p)
     // so many short segments beat fewer tall ones down to about 8 rows.
     mdf::FusedShape sh;
     sh.tile_w = 64;
+    sh.prefetch = 2;
     const int nstrips = (p.nx + sh.tile_w - 9) / (sh.tile_w - 8);
     int nseg = 4096 / (nstrips > 0 ? nstrips : 1);
     if (nseg < 1) nseg = 1;
@@ -268,8 +277,10 @@ mdf_status mdf_step(mdf_ctx* c, int64_t n)
         hipError_t e;
         if (c->variant == 0)
             e = mdf::launch_three_pass(c->K, fin, c->fbp, c->fmid, fout, c->stream);
-        else
+        else if (c->variant == 1)
             e = mdf::launch_fused(c->K, c->shape, fin, fout, c->stream);
+        else
+            e = mdf::launch_fused2(c->K, c->shape, fin, fout, c->stream);
         if (e != hipSuccess) return hip_check(c, e, "step launch");
         c->cur = 1 - c->cur;
         c->steps += 1;
@@ -322,15 +333,16 @@ mdf_status mdf_load(mdf_ctx* c, const double* f)
     return hip_check(c, mdf::launch_unpack(c->K, f, c->f[c->cur], c->stream), "load launch");
 }
 
-mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t seg_h)
+mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t seg_h, int32_t prefetch)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
-    if (variant != 0 && variant != 1) return fail(c, MDF_EINVAL, "variant must be 0 or 1");
+    if (variant < 0 || variant > 2) return fail(c, MDF_EINVAL, "variant must be 0, 1 or 2");
     mdf::FusedShape sh = c->shape;
     if (tile_w) sh.tile_w = tile_w;
     if (seg_h) sh.seg_h = seg_h;
+    if (prefetch) sh.prefetch = prefetch;
     if (!mdf::fused_shape_ok(c->K, sh))
-        return fail(c, MDF_EINVAL, "tile_w must be 64, 128 or 256 and seg_h >= 1");
+        return fail(c, MDF_EINVAL, "tile_w must be 64 or 128, seg_h >= 1 and prefetch 2 or 3");
     c->variant = variant;
     c->shape = sh;
     return MDF_OK;

@@ -1,5 +1,5 @@
 // Auxiliary kernels: initialisation, wall rule on a stored field, moments,
-// local derived quantities, diagnostics reductions, plane copies, and the
+// local derived quantities, diagnostics reductions, state copies, and the
 // three-pass reference time step (one kernel per sub-step of Sec. 2.2).
 #include "mdf_device.hpp"
 #include "mdf_internal.hpp"
@@ -8,18 +8,20 @@ namespace mdf {
 
 namespace {
 
-__device__ __forceinline__ long long nidx(const StepConsts& K, int x, int y) { return (long long)y * K.pitch + x; }
-
-__device__ __forceinline__ void load10(const StepConsts& K, const double* f, long long i, double* phi)
+__device__ __forceinline__ void load10(const StepConsts& K, const double* f, int x, int y, double* phi)
 {
-#pragma unroll
-    for (int k = 0; k < 10; ++k) phi[k] = f[k * K.plane + i];
+    load_node(f, K.pitch, x, y, phi);
 }
 
-__device__ __forceinline__ void store10(const StepConsts& K, double* f, long long i, const double* phi)
+__device__ __forceinline__ void store10(const StepConsts& K, double* f, int x, int y, const double* phi)
 {
-#pragma unroll
-    for (int k = 0; k < 10; ++k) f[k * K.plane + i] = phi[k];
+    store_node(f, K.pitch, x, y, phi);
+}
+
+// component q (= alpha*5 + j) of node (x, y)
+__device__ __forceinline__ double comp(const StepConsts& K, const double* f, int x, int y, int q)
+{
+    return f[comp_off(K.pitch, x, y, q)];
 }
 
 // inward neighbours of a wall node; returns false for interior nodes
@@ -39,36 +41,38 @@ __device__ __forceinline__ bool wall_neighbours(const StepConsts& K, int x, int 
     return true;
 }
 
-// value of one plane at (x, y) where one coordinate may be one node beyond a
-// wall (quadratic ghost) or outside a periodic range (wrapped)
-__device__ __forceinline__ double fetch(const StepConsts& K, const double* pl, int x, int y)
+// component q at (x, y) where one coordinate may be one node beyond a wall
+// (quadratic ghost) or outside a periodic range (wrapped)
+__device__ __forceinline__ double fetch(const StepConsts& K, const double* f, int q, int x, int y)
 {
     if (!K.bcx) x = x < 0 ? x + K.nx : (x >= K.nx ? x - K.nx : x);
     if (!K.bcy) y = y < 0 ? y + K.ny : (y >= K.ny ? y - K.ny : y);
-    if (x == -1) return ghost(pl[nidx(K, 0, y)], pl[nidx(K, 1, y)], pl[nidx(K, 2, y)]);
-    if (x == K.nx) return ghost(pl[nidx(K, K.nx - 1, y)], pl[nidx(K, K.nx - 2, y)], pl[nidx(K, K.nx - 3, y)]);
-    if (y == -1) return ghost(pl[nidx(K, x, 0)], pl[nidx(K, x, 1)], pl[nidx(K, x, 2)]);
-    if (y == K.ny) return ghost(pl[nidx(K, x, K.ny - 1)], pl[nidx(K, x, K.ny - 2)], pl[nidx(K, x, K.ny - 3)]);
-    return pl[nidx(K, x, y)];
+    if (x == -1) return ghost(comp(K, f, 0, y, q), comp(K, f, 1, y, q), comp(K, f, 2, y, q));
+    if (x == K.nx)
+        return ghost(comp(K, f, K.nx - 1, y, q), comp(K, f, K.nx - 2, y, q),
+                     comp(K, f, K.nx - 3, y, q));
+    if (y == -1) return ghost(comp(K, f, x, 0, q), comp(K, f, x, 1, q), comp(K, f, x, 2, q));
+    if (y == K.ny)
+        return ghost(comp(K, f, x, K.ny - 1, q), comp(K, f, x, K.ny - 2, q),
+                     comp(K, f, x, K.ny - 3, q));
+    return comp(K, f, x, y, q);
 }
 
-// tau c_j . grad Pi_j at an interior node (lam = tau c / 2)
-__device__ __forceinline__ double transport_at(const StepConsts& K, const double* f, int plane_k, int x, int y,
-                                               double lam)
+// tau c_j . grad Pi_j at an interior node (lam = tau c / 2), component q = alpha*5 + j
+__device__ __forceinline__ double transport_at(const StepConsts& K, const double* f, int q, int x, int y, double lam)
 {
-    const int j = plane_k % 5;
-    const double* pl = f + plane_k * K.plane;
+    const int j = q % 5;
     if (j == 0) return 0.0;
     if (j == 1 || j == 3) {
         const double lg = lam * K.gx[x];
-        const double pm1 = fetch(K, pl, x - 1, y), p0 = fetch(K, pl, x, y), p1 = fetch(K, pl, x + 1, y);
-        if (j == 1) return transport_pos(K, lg, fetch(K, pl, x - 2, y), pm1, p0, p1);
-        return transport_neg(K, lg, pm1, p0, p1, fetch(K, pl, x + 2, y));
+        const double pm1 = fetch(K, f, q, x - 1, y), p0 = fetch(K, f, q, x, y), p1 = fetch(K, f, q, x + 1, y);
+        if (j == 1) return transport_pos(K, lg, fetch(K, f, q, x - 2, y), pm1, p0, p1);
+        return transport_neg(K, lg, pm1, p0, p1, fetch(K, f, q, x + 2, y));
     }
     const double lg = lam * K.gy[y];
-    const double pm1 = fetch(K, pl, x, y - 1), p0 = fetch(K, pl, x, y), p1 = fetch(K, pl, x, y + 1);
-    if (j == 2) return transport_pos(K, lg, fetch(K, pl, x, y - 2), pm1, p0, p1);
-    return transport_neg(K, lg, pm1, p0, p1, fetch(K, pl, x, y + 2));
+    const double pm1 = fetch(K, f, q, x, y - 1), p0 = fetch(K, f, q, x, y), p1 = fetch(K, f, q, x, y + 1);
+    if (j == 2) return transport_pos(K, lg, fetch(K, f, q, x, y - 2), pm1, p0, p1);
+    return transport_neg(K, lg, pm1, p0, p1, fetch(K, f, q, x, y + 2));
 }
 
 __global__ void k_init(StepConsts K, const double* __restrict__ u0, const double* __restrict__ v0,
@@ -79,7 +83,7 @@ __global__ void k_init(StepConsts K, const double* __restrict__ u0, const double
     const long long s = (long long)y * K.nx + x;
     double fe[10];
     equilibrium(u0[s], v0[s], p0[s], K, fe);
-    store10(K, f, nidx(K, x, y), fe);
+    store10(K, f, x, y, fe);
 }
 
 // wall rule applied to the wall nodes of a stored 10-plane field
@@ -91,10 +95,10 @@ __global__ void k_wall_fix(StepConsts K, double* __restrict__ f)
     double uw;
     if (!wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) return;
     double p1[10], p2[10], out[10];
-    load10(K, f, nidx(K, x1, y1), p1);
-    load10(K, f, nidx(K, x2, y2), p2);
+    load10(K, f, x1, y1, p1);
+    load10(K, f, x2, y2, p2);
     wall_extrapolate(K, p1, p2, uw, out);
-    store10(K, f, nidx(K, x, y), out);
+    store10(K, f, x, y, out);
 }
 
 __global__ void k_moments(StepConsts K, const double* __restrict__ f, double* __restrict__ u, double* __restrict__ v,
@@ -103,7 +107,7 @@ __global__ void k_moments(StepConsts K, const double* __restrict__ f, double* __
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= K.nx || y >= K.ny) return;
     double phi[10], uu, vv, PP;
-    load10(K, f, nidx(K, x, y), phi);
+    load10(K, f, x, y, phi);
     node_moments(phi, K.c, uu, vv, PP);
     const long long s = (long long)y * K.nx + x;
     if (u) u[s] = uu;
@@ -147,7 +151,7 @@ __global__ void k_derived(StepConsts K, const double* __restrict__ f, double* __
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= K.nx || y >= K.ny) return;
     double fh[10], d[14];
-    load10(K, f, nidx(K, x, y), fh);
+    load10(K, f, x, y, fh);
     derived_node(K, fh, d);
     const long long n = (long long)K.nx * K.ny, s = (long long)y * K.nx + x;
     int slot = 0;
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
     for (long long s = (long long)blockIdx.x * DIAG_BLOCK + threadIdx.x; s < n; s += (long long)gridDim.x * DIAG_BLOCK) {
         const int x = (int)(s % K.nx), y = (int)(s / K.nx);
         double fh[10], d[14], u, v, P;
-        load10(K, f, nidx(K, x, y), fh);
+        load10(K, f, x, y, fh);
         node_moments(fh, K.c, u, v, P);
         derived_node(K, fh, d);
         const double dA = 1.0 / (K.gx[x] * K.gy[y]);
@@ -213,13 +217,13 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
             const int xp = x + 1 == K.nx ? 0 : x + 1, xm = x == 0 ? K.nx - 1 : x - 1;
             const int yp = y + 1 == K.ny ? 0 : y + 1, ym = y == 0 ? K.ny - 1 : y - 1;
             double a[10], b[10], t0, t1, t2, ue, uw, vn, vs;
-            load10(K, f, nidx(K, xp, y), a);
+            load10(K, f, xp, y, a);
             node_moments(a, K.c, ue, t1, t2);
-            load10(K, f, nidx(K, xm, y), b);
+            load10(K, f, xm, y, b);
             node_moments(b, K.c, uw, t1, t2);
-            load10(K, f, nidx(K, x, yp), a);
+            load10(K, f, x, yp, a);
             node_moments(a, K.c, t0, vn, t2);
-            load10(K, f, nidx(K, x, ym), b);
+            load10(K, f, x, ym, b);
             node_moments(b, K.c, t0, vs, t2);
             const double div = (ue - uw) * K.gx[x] * 0.5 + (vn - vs) * K.gy[y] * 0.5;
             acc[5] = fmax(acc[5], fabs(div));
@@ -254,7 +258,7 @@ __global__ void k_pack(StepConsts K, const double* __restrict__ f, double* __res
     if (x >= K.nx || y >= K.ny) return;
     const long long n = (long long)K.nx * K.ny, s = (long long)y * K.nx + x;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) dense[k * n + s] = f[k * K.plane + nidx(K, x, y)];
+    for (int k = 0; k < 10; ++k) dense[k * n + s] = comp(K, f, x, y, k);
 }
 
 __global__ void k_unpack(StepConsts K, const double* __restrict__ dense, double* __restrict__ f)
@@ -262,8 +266,10 @@ __global__ void k_unpack(StepConsts K, const double* __restrict__ dense, double*
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= K.nx || y >= K.ny) return;
     const long long n = (long long)K.nx * K.ny, s = (long long)y * K.nx + x;
+    double phi[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) f[k * K.plane + nidx(K, x, y)] = dense[k * n + s];
+    for (int k = 0; k < 10; ++k) phi[k] = dense[k * n + s];
+    store_node(f, K.pitch, x, y, phi);
 }
 
 // ---- three-pass reference step ----
@@ -277,26 +283,25 @@ __global__ void k_pass_a(StepConsts K, const double* __restrict__ fh, double* __
     double uw, a[10], out[10];
     if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
         double b[10], p1[10], p2[10];
-        load10(K, fh, nidx(K, x1, y1), a);
+        load10(K, fh, x1, y1, a);
         collide1_bar(K, a, p1);
-        load10(K, fh, nidx(K, x2, y2), b);
+        load10(K, fh, x2, y2, b);
         collide1_bar(K, b, p2);
         wall_extrapolate(K, p1, p2, uw, out);
     } else {
-        load10(K, fh, nidx(K, x, y), a);
+        load10(K, fh, x, y, a);
         collide1_bar(K, a, out);
     }
-    store10(K, fbp, nidx(K, x, y), out);
+    store10(K, fbp, x, y, out);
 }
 
 // f(t+h) at an interior node: half step (eq. 2.3.25 in Taylor form) then Step (3)
 __device__ __forceinline__ void mid_at(const StepConsts& K, const double* fbp, int x, int y, double* f)
 {
     double fb[10];
-    const long long i = nidx(K, x, y);
 #pragma unroll
     for (int k = 0; k < 10; ++k)
-        fb[k] = fbp[k * K.plane + i] - transport_at(K, fbp, k, x, y, K.lam_h) + K.hwf[k / 5];
+        fb[k] = comp(K, fbp, x, y, k) - transport_at(K, fbp, k, x, y, K.lam_h) + K.hwf[k / 5];
     collide3(K, fb, f);
 }
 
@@ -314,7 +319,7 @@ __global__ void k_pass_b(StepConsts K, const double* __restrict__ fbp, double* _
     } else {
         mid_at(K, fbp, x, y, out);
     }
-    store10(K, fmid, nidx(K, x, y), out);
+    store10(K, fmid, x, y, out);
 }
 
 // f_hat(t+dt) at an interior node: Step (4), eq. 2.3.24
@@ -322,7 +327,7 @@ __device__ __forceinline__ void full_at(const StepConsts& K, const double* fh, c
                                         double* out)
 {
     double a[10], fhp[10];
-    load10(K, fh, nidx(K, x, y), a);
+    load10(K, fh, x, y, a);
     collide1_hat(K, a, fhp);
 #pragma unroll
     for (int k = 0; k < 10; ++k) out[k] = fhp[k] - transport_at(K, fmid, k, x, y, K.lam_dt) + K.dwf[k / 5];
@@ -343,7 +348,7 @@ __global__ void k_pass_c(StepConsts K, const double* __restrict__ fh, const doub
     } else {
         full_at(K, fh, fmid, x, y, out);
     }
-    store10(K, fnew, nidx(K, x, y), out);
+    store10(K, fnew, x, y, out);
 }
 
 inline dim3 grid2d(const StepConsts& K, dim3 b) { return dim3((K.nx + b.x - 1) / b.x, (K.ny + b.y - 1) / b.y); }

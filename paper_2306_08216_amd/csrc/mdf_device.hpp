@@ -26,12 +26,14 @@ struct StepConsts {
     int nx, ny;
     int bcx, bcy;            // 0 periodic, 1 wall
     int pl;                  // PL_*
-    int pitch;               // doubles per row
-    long long plane;         // doubles per plane
+    int pitch;               // nodes per row of the node-major state (>= nx)
     double c, w, kf;         // lattice speed, weight 1/5, w c / c_s^2
     double cs2, dt, h;
     double eta, one_m_eta;
     double st_a, st_b, st_c, st_d;   // mixed-difference weights (see transport_pos)
+    int uniform;                     // both axes uniform: stencil coefficients below are valid
+    double sh[2][4], sd[2][4];       // folded stencils per axis for the half (tau = h, centre + 1)
+                                     // and full (tau = dt) updates, see make_stencil
     double lid_u;
     // Newtonian relaxation factors for (s, s')
     double a_s, a_p, b_s, b_p, q_s, q_p;
@@ -45,6 +47,108 @@ struct StepConsts {
     const double* gx;        // nx derivative scales 1/(X' dxi)
     const double* gy;        // ny derivative scales
 };
+
+// State layout (row-split).  Row y occupies 80*pitch contiguous bytes: first
+// the x-part block, pitch nodes x 6 doubles holding the components streamed
+// along x or not at all (j = 0, 1, 3 of the u set, then of the v set), then the
+// y-part block, pitch nodes x 4 doubles holding the components streamed along
+// y (j = 2, 4 of the u set, then of the v set).  A fused step writes the x
+// part and the y part of a node at different times (the y stencil needs two
+// more rows); with this split each write covers whole cache lines of one
+// block.  Components are numbered q = alpha*5 + j as in the method.
+__host__ __device__ constexpr int comp_slot(int q)   // slot within its block
+{
+    return (q % 5 == 2 || q % 5 == 4) ? 2 * (q / 5) + (q % 5 == 4) : 3 * (q / 5) + (q % 5 == 0 ? 0 : (q % 5 == 1 ? 1 : 2));
+}
+__host__ __device__ constexpr bool comp_in_xpart(int q) { return !(q % 5 == 2 || q % 5 == 4); }
+
+__device__ __forceinline__ size_t xpart_off(int pitch, int x, int y) { return (size_t)y * pitch * 10 + (size_t)x * 6; }
+__device__ __forceinline__ size_t ypart_off(int pitch, int x, int y)
+{
+    return (size_t)y * pitch * 10 + (size_t)pitch * 6 + (size_t)x * 4;
+}
+__device__ __forceinline__ size_t comp_off(int pitch, int x, int y, int q)
+{
+    return comp_in_xpart(q) ? xpart_off(pitch, x, y) + comp_slot(q) : ypart_off(pitch, x, y) + comp_slot(q);
+}
+
+__device__ __forceinline__ void load_node(const double* __restrict__ f, int pitch, int x, int y, double* phi)
+{
+    const double2* px = reinterpret_cast<const double2*>(f + xpart_off(pitch, x, y));
+    const double2* py = reinterpret_cast<const double2*>(f + ypart_off(pitch, x, y));
+    const double2 a = px[0], b = px[1], c = px[2], d = py[0], e = py[1];
+    phi[0] = a.x; phi[1] = a.y; phi[3] = b.x;   // u set j = 0, 1, 3
+    phi[5] = b.y; phi[6] = c.x; phi[8] = c.y;   // v set j = 0, 1, 3
+    phi[2] = d.x; phi[4] = d.y;                 // u set j = 2, 4
+    phi[7] = e.x; phi[9] = e.y;                 // v set j = 2, 4
+}
+
+__device__ __forceinline__ void store_node(double* __restrict__ f, int pitch, int x, int y, const double* phi)
+{
+    double2* px = reinterpret_cast<double2*>(f + xpart_off(pitch, x, y));
+    double2* py = reinterpret_cast<double2*>(f + ypart_off(pitch, x, y));
+    px[0] = make_double2(phi[0], phi[1]);
+    px[1] = make_double2(phi[3], phi[5]);
+    px[2] = make_double2(phi[6], phi[8]);
+    py[0] = make_double2(phi[2], phi[4]);
+    py[1] = make_double2(phi[7], phi[9]);
+}
+
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// fences global memory, which makes every wave drain its outstanding global
+// loads (vmcnt 0) at the barrier and so cancels any row prefetch in flight.
+// The fused kernels exchange data between waves through LDS alone, so the
+// barrier only needs LDS (lgkm) completion.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Exchange barrier for a workgroup of NW waves.  One wave needs no hardware
+// barrier: LDS executes a wave's accesses in issue order, so only the compiler
+// must be kept from moving LDS accesses across the exchange point.
+template <int NW>
+__device__ __forceinline__ void exchange_barrier()
+{
+    if constexpr (NW == 1) {
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        lds_barrier();
+    }
+}
+
+// Raw buffer access to one row of the state.  The descriptor lives in scalar
+// registers; with stride 0 the hardware checks each access against
+// num_records: loads past it return zero and stores past it are dropped.
+typedef __amdgpu_buffer_rsrc_t BufRes;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef int ivec4 __attribute__((ext_vector_type(4)));
+typedef int ivec2 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;   // 32-bit data format for gfx9 raw buffers
+
+// descriptor of row `row` (row_bytes bytes) of f; `on` false gives no records
+__device__ __forceinline__ BufRes row_res(const double* f, int row_bytes, int row, bool on)
+{
+    const char* p = reinterpret_cast<const char*>(f) + (size_t)row * (size_t)row_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, on ? row_bytes : 0, kBufWord3);
+}
+
+__device__ __forceinline__ dvec2 buf_load2(BufRes r, unsigned off)
+{
+    return __builtin_bit_cast(dvec2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void buf_store2(BufRes r, unsigned off, dvec2 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(ivec4, v), r, off, 0, 0);
+}
+
+__device__ __forceinline__ void buf_store1(BufRes r, unsigned off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(ivec2, v), r, off, 0, 0);
+}
 
 struct Relax {               // a relaxation pair kappa (rate s), kappa' (rate s')
     double k, kp;
@@ -258,6 +362,31 @@ __device__ __forceinline__ double transport_neg(const StepConsts& K, double lamg
                                                 double p2)
 {
     return lamg * (K.st_d * pm1 + K.st_c * p0 + K.st_b * p1 + K.st_a * p2);
+}
+
+// Folded stencil of one axis: new = base + k_a Pm2 + k_b Pm1 + k_c P0 + k_d P1
+// for c > 0 (mirror order for c < 0), with k_x = -lamg w_x, plus 1 on the
+// centre weight when the stenciled field itself is the one being advanced
+// (the half step f_bar = f_bar^+ - h c.grad f_bar^+).  Four FMAs per update.
+struct Stencil {
+    double a, b, c, d;
+};
+
+__host__ __device__ inline Stencil make_stencil(const StepConsts& K, double lamg, bool centre_one)
+{
+    return Stencil{-lamg * K.st_a, -lamg * K.st_b, (centre_one ? 1.0 : 0.0) - lamg * K.st_c, -lamg * K.st_d};
+}
+
+__device__ __forceinline__ Stencil stencil_of(const double* s4) { return Stencil{s4[0], s4[1], s4[2], s4[3]}; }
+
+__device__ __forceinline__ double upd_pos(const Stencil& k, double base, double pm2, double pm1, double p0, double p1)
+{
+    return fma(k.d, p1, fma(k.c, p0, fma(k.b, pm1, fma(k.a, pm2, base))));
+}
+
+__device__ __forceinline__ double upd_neg(const Stencil& k, double base, double pm1, double p0, double p1, double p2)
+{
+    return fma(k.a, p2, fma(k.b, p1, fma(k.c, p0, fma(k.d, pm1, base))));
 }
 
 __device__ __forceinline__ double ghost(double p0, double p1, double p2) { return 3.0 * p0 - 3.0 * p1 + p2; }

@@ -61,13 +61,13 @@ __device__ __forceinline__ int lclamp(int l)
 // by the ghost node.  comp c = (alpha = c/2, j = 1 if c even else 3).
 template <int TW, bool WX>
 __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW], int lane, int x, double nb[4][5],
-                                             double lid)
+                                             bool wall_strip)
 {
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int d = -2; d <= 2; ++d) nb[c][d + 2] = X[c][lclamp<TW>(lane + d)];
-    if (WX) {
+    if (WX && wall_strip) {
         if (x >= 1 && x <= 2) {
             const int l1 = lclamp<TW>(lane + (1 - x)), l2 = lclamp<TW>(lane + (2 - x));
             const double m1[3] = {X[4][l1], X[5][l1], X[6][l1]};
@@ -99,10 +99,9 @@ __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW
             }
         }
     }
-    (void)lid;
 }
 
-template <int TW, bool WX, bool WY, bool PLW>
+template <int TW, bool WX, bool WY, bool PLW, int PF, bool UNI>
 __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __restrict__ fin, double* __restrict__ fout,
                                               FusedGrid G)
 {
@@ -112,10 +111,11 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
     const int L = (int)(blockIdx.x % 8) * G.chunk + (int)(blockIdx.x / 8);
     if (L >= G.nstrips * G.nsegs) return;
     const int strip = L / G.nsegs, seg = L - strip * G.nsegs;
-    const int xs0 = (int)((long long)strip * K.nx / G.nstrips);
-    const int xs1 = (int)((long long)(strip + 1) * K.nx / G.nstrips);
-    const int ys0 = (int)((long long)seg * K.ny / G.nsegs);
-    const int ys1 = (int)((long long)(seg + 1) * K.ny / G.nsegs);
+    // balanced partitions (products stay below 2^31 for any grid the ABI accepts)
+    const int xs0 = (int)((unsigned)(strip * K.nx) / (unsigned)G.nstrips);
+    const int xs1 = (int)((unsigned)((strip + 1) * K.nx) / (unsigned)G.nstrips);
+    const int ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
+    const int ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
 
     const int lane = threadIdx.x;
     const int x = xs0 - 4 + lane;
@@ -127,9 +127,30 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
         if (xg < 0) xg += K.nx;
     }
     const bool outc = (x >= xs0) && (x < xs1) && (!WX || (x >= 1 && x <= K.nx - 2));
-    const double gxl = K.gx[xg];
-    const double lhx = K.lam_h * gxl, ldx = K.lam_dt * gxl;
-    const long long pl = K.plane;
+    // workgroup-uniform: only strips holding lanes for columns 1-2 or nx-3..nx-2
+    // (lanes span xs0-4 .. xs1+3) and segments whose march reaches rows 0-2 or
+    // ny-3..ny-1 run the wall-rule code; the margin of 8 is generous
+    const bool wall_strip = WX && (xs0 <= 8 || xs1 >= K.nx - 8);
+    const bool wall_seg = WY && (ys0 <= 8 || ys1 >= K.ny - 8);
+    // x stencils: constants on a uniform grid, per lane (column) on a mapped one
+    const double gxl = UNI ? 0.0 : K.gx[xg];
+    const Stencil SXh = UNI ? stencil_of(K.sh[0]) : make_stencil(K, K.lam_h * gxl, true);
+    const Stencil SXd = UNI ? stencil_of(K.sd[0]) : make_stencil(K, K.lam_dt * gxl, false);
+    auto y_stencil_h = [&](int row) -> Stencil {
+        return UNI ? stencil_of(K.sh[1]) : make_stencil(K, K.lam_h * K.gy[row], true);
+    };
+    auto y_stencil_d = [&](int row) -> Stencil {
+        return UNI ? stencil_of(K.sd[1]) : make_stencil(K, K.lam_dt * K.gy[row], false);
+    };
+    // Every row access goes through a buffer descriptor of that one row
+    // (scalar registers), so the lane offsets below are the only vector
+    // addresses.  A row that must not be touched gets zero records: its loads
+    // return 0 (rows beyond a y wall) and its stores are dropped; halo lanes
+    // store to an offset past the end of the row.
+    // byte offsets of this lane's node within a row: x-part block, y-part block
+    const unsigned vx = (unsigned)xg * 48u, vy = (unsigned)K.pitch * 48u + (unsigned)xg * 32u;
+    const unsigned vx_st = outc ? vx : 0x7fffff00u, vy_st = outc ? vy : 0x7fffff00u;
+    const int row_bytes = K.pitch * 80;
 
     auto wrap_y = [&](int k) -> int {
         if (WY) return k;
@@ -137,18 +158,25 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
     };
     auto row_ok = [&](int k) -> bool { return WY ? (k >= 0 && k < K.ny) : true; };
 
+    // rows kbeg..kend enter the march, padded to whole 4-row groups (the
+    // padding rows reach no output) so the unrolled loop has no partial group
     const int kbeg = ys0 - 4, kend = ys1 + 3;
+    const int kpad = kbeg + ((kend - kbeg + 4) & ~3) - 1;
 
-    double nxt[10];
+    // prefetch ring: row k lives in slot (k - kbeg) & 3 and is requested PF rows
+    // ahead.  Every body issues the same loads and stores whatever its row, so
+    // the compiler counts the memory operations in flight exactly and waits
+    // only for the row it consumes.
+    double pre[4][10];
     auto load_row = [&](int k, double* dst) {
-        if (row_ok(k)) {
-            const double* p = fin + (long long)wrap_y(k) * K.pitch + xg;
-#pragma unroll
-            for (int q = 0; q < 10; ++q) dst[q] = p[q * pl];
-        } else {
-#pragma unroll
-            for (int q = 0; q < 10; ++q) dst[q] = 0.0;
-        }
+        const bool on = k <= kend && row_ok(k);   // rows past kend are never used
+        const BufRes rs = row_res(fin, row_bytes, on ? wrap_y(k) : 0, on);
+        const dvec2 a = buf_load2(rs, vx), b = buf_load2(rs, vx + 16u), c = buf_load2(rs, vx + 32u);
+        const dvec2 d = buf_load2(rs, vy), e = buf_load2(rs, vy + 16u);
+        dst[0] = a.x; dst[1] = a.y; dst[3] = b.x;   // x part: j = 0, 1, 3 of each set
+        dst[5] = b.y; dst[6] = c.x; dst[8] = c.y;
+        dst[2] = d.x; dst[4] = d.y;                 // y part: j = 2, 4 of each set
+        dst[7] = e.x; dst[9] = e.y;
     };
 
     double W2[4][2], W4[4][2], F2[4][2], F4[4][2], Qy[4][4], Qx[2][6], Qb[2][6];
@@ -164,15 +192,16 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
 #pragma unroll
         for (int q = 0; q < 6; ++q) Qx[i][q] = Qb[i][q] = 0.0;
 
-    load_row(kbeg, nxt);
+#pragma unroll
+    for (int i = 0; i < PF; ++i) load_row(kbeg + i, pre[i]);
 
     auto body = [&](auto PC, int k) {
         constexpr int P = decltype(PC)::value;
         constexpr int S1 = (P + 3) & 3, S2 = (P + 2) & 3, S3 = (P + 1) & 3;   // rows k-1, k-2, k-3
         double cur[10];
 #pragma unroll
-        for (int q = 0; q < 10; ++q) cur[q] = nxt[q];
-        if (k + 1 <= kend) load_row(k + 1, nxt);
+        for (int q = 0; q < 10; ++q) cur[q] = pre[P][q];
+        load_row(k + PF, pre[(P + PF) & 3]);
 
         // ---- A: Step (1) on row k ----
         double fbp[10], fhp[10], ub[3];
@@ -193,7 +222,7 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
         double b2[2] = {fbp[2], fbp[7]};
         W4[P][0] = fbp[4];
         W4[P][1] = fbp[9];
-        if (WY) {
+        if (WY && wall_seg) {
             if (k == 2) {   // bottom wall row 0 from rows 1 and 2
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
@@ -224,22 +253,20 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
             X[1][lane] = fbp[3];
             X[2][lane] = fbp[6];
             X[3][lane] = fbp[8];
-            if (WX) {
+            if (WX && wall_strip) {
                 X[4][lane] = ub[0];
                 X[5][lane] = ub[1];
                 X[6][lane] = ub[2];
             }
-            __syncthreads();
+            exchange_barrier<TW / 64>();
             double nb[4][5];
-            x_neighbours<TW, WX>(K, X, lane, x, nb, 0.0);
+            x_neighbours<TW, WX>(K, X, lane, x, nb, wall_strip);
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 bx[3 * a + 0] = fbp[5 * a] + K.hwf[a];
-                bx[3 * a + 1] = fbp[5 * a + 1] -
-                                transport_pos(K, lhx, nb[2 * a][0], nb[2 * a][1], nb[2 * a][2], nb[2 * a][3]) + K.hwf[a];
-                bx[3 * a + 2] = fbp[5 * a + 3] -
-                                transport_neg(K, lhx, nb[2 * a + 1][1], nb[2 * a + 1][2], nb[2 * a + 1][3],
-                                              nb[2 * a + 1][4]) + K.hwf[a];
+                bx[3 * a + 1] = upd_pos(SXh, K.hwf[a], nb[2 * a][0], nb[2 * a][1], nb[2 * a][2], nb[2 * a][3]);
+                bx[3 * a + 2] =
+                    upd_neg(SXh, K.hwf[a], nb[2 * a + 1][1], nb[2 * a + 1][2], nb[2 * a + 1][3], nb[2 * a + 1][4]);
             }
         }
 
@@ -247,21 +274,21 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
         const int m = k - 2;
         const bool needB = (m >= ys0 - 2) && (m < ys1 + 2) && (WY ? (m >= 1 && m <= K.ny - 2) : true);
         double f2c[2] = {0.0, 0.0};
-        double fm[10], uf[3] = {0.0, 0.0, 0.0};
+        double fm[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, uf[3] = {0.0, 0.0, 0.0};
         if (needB) {
-            const double lhy = K.lam_h * K.gy[wrap_y(m)];
+            const Stencil SYh = y_stencil_h(wrap_y(m));
             double fb[10];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 double a2[4] = {W2[P][a], W2[S3][a], W2[S2][a], W2[S1][a]};   // rows m-2 .. m+1
                 double a4[4] = {W4[S3][a], W4[S2][a], W4[S1][a], W4[P][a]};   // rows m-1 .. m+2
-                if (WY && m == 1) a2[0] = ghost(a2[1], a2[2], a2[3]);
-                if (WY && m == K.ny - 2) a4[3] = ghost(a4[2], a4[1], a4[0]);
+                if (WY && wall_seg && m == 1) a2[0] = ghost(a2[1], a2[2], a2[3]);
+                if (WY && wall_seg && m == K.ny - 2) a4[3] = ghost(a4[2], a4[1], a4[0]);
                 fb[5 * a + 0] = Qb[P & 1][3 * a + 0];
                 fb[5 * a + 1] = Qb[P & 1][3 * a + 1];
                 fb[5 * a + 3] = Qb[P & 1][3 * a + 2];
-                fb[5 * a + 2] = a2[2] - transport_pos(K, lhy, a2[0], a2[1], a2[2], a2[3]) + K.hwf[a];
-                fb[5 * a + 4] = a4[1] - transport_neg(K, lhy, a4[0], a4[1], a4[2], a4[3]) + K.hwf[a];
+                fb[5 * a + 2] = upd_pos(SYh, K.hwf[a], a2[0], a2[1], a2[2], a2[3]);
+                fb[5 * a + 4] = upd_neg(SYh, K.hwf[a], a4[0], a4[1], a4[2], a4[3]);
             }
             double fe[10];
             node_moments(fb, K.c, uf[0], uf[1], uf[2]);
@@ -273,7 +300,7 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
             f2c[0] = fm[2];
             f2c[1] = fm[7];
         }
-        if (WY) {
+        if (WY && wall_seg) {
             if (m == 2) {   // bottom wall row 0 of f(t+h)
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
@@ -298,57 +325,55 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
 
         // ---- B': x part of Step (4) on row m ----
         const bool outm = needB && (m >= ys0) && (m < ys1);
-        if (outm) {
+        {
+            double h[2][3];
             double(*X)[TW] = xs[1];
             X[0][lane] = fm[1];
             X[1][lane] = fm[3];
             X[2][lane] = fm[6];
             X[3][lane] = fm[8];
-            if (WX) {
+            if (WX && wall_strip) {
                 X[4][lane] = uf[0];
                 X[5][lane] = uf[1];
                 X[6][lane] = uf[2];
             }
-            __syncthreads();
+            exchange_barrier<TW / 64>();
             double nb[4][5];
-            x_neighbours<TW, WX>(K, X, lane, x, nb, 0.0);
-            if (outc) {
-                double* o = fout + (long long)wrap_y(m) * K.pitch + xg;
+            x_neighbours<TW, WX>(K, X, lane, x, nb, wall_strip);
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const double h0 = Qx[P & 1][3 * a + 0] + K.dwf[a];
-                    const double h1 = Qx[P & 1][3 * a + 1] -
-                                      transport_pos(K, ldx, nb[2 * a][0], nb[2 * a][1], nb[2 * a][2], nb[2 * a][3]) +
-                                      K.dwf[a];
-                    const double h3 = Qx[P & 1][3 * a + 2] -
-                                      transport_neg(K, ldx, nb[2 * a + 1][1], nb[2 * a + 1][2], nb[2 * a + 1][3],
-                                                    nb[2 * a + 1][4]) + K.dwf[a];
-                    o[(5 * a + 0) * pl] = h0;
-                    o[(5 * a + 1) * pl] = h1;
-                    o[(5 * a + 3) * pl] = h3;
-                }
+            for (int a = 0; a < 2; ++a) {
+                h[a][0] = Qx[P & 1][3 * a + 0] + K.dwf[a];
+                h[a][1] = upd_pos(SXd, Qx[P & 1][3 * a + 1] + K.dwf[a], nb[2 * a][0], nb[2 * a][1], nb[2 * a][2],
+                                  nb[2 * a][3]);
+                h[a][2] = upd_neg(SXd, Qx[P & 1][3 * a + 2] + K.dwf[a], nb[2 * a + 1][1], nb[2 * a + 1][2],
+                                  nb[2 * a + 1][3], nb[2 * a + 1][4]);
             }
-        } else {
-            __syncthreads();   // keeps the two LDS buffers strictly alternating
+            // x part of row m is final: one contiguous 48 B block per node
+            const BufRes rs = row_res(fout, row_bytes, outm ? wrap_y(m) : 0, outm);
+            buf_store2(rs, vx_st, dvec2{h[0][0], h[0][1]});
+            buf_store2(rs, vx_st + 16u, dvec2{h[0][2], h[1][0]});
+            buf_store2(rs, vx_st + 32u, dvec2{h[1][1], h[1][2]});
         }
 
         // ---- C: y part of Step (4) on row r = k-4 ----
         const int r = k - 4;
         const bool outr = (r >= ys0) && (r < ys1) && (WY ? (r >= 1 && r <= K.ny - 2) : true);
-        if (outr && outc) {
-            const double ldy = K.lam_dt * K.gy[wrap_y(r)];
-            double* o = fout + (long long)wrap_y(r) * K.pitch + xg;
+        {
+            const Stencil SYd = y_stencil_d(outr ? wrap_y(r) : ys0);
+            double hy[2][2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 double c2[4] = {F2[S2][a], F2[S1][a], F2[P][a], F2[S3][a]};   // rows r-2 .. r+1
                 double c4[4] = {F4[S1][a], F4[P][a], F4[S3][a], F4[S2][a]};   // rows r-1 .. r+2
-                if (WY && r == 1) c2[0] = ghost(c2[1], c2[2], c2[3]);
-                if (WY && r == K.ny - 2) c4[3] = ghost(c4[2], c4[1], c4[0]);
-                const double h2 = Qy[P][2 * a] - transport_pos(K, ldy, c2[0], c2[1], c2[2], c2[3]) + K.dwf[a];
-                const double h4 = Qy[P][2 * a + 1] - transport_neg(K, ldy, c4[0], c4[1], c4[2], c4[3]) + K.dwf[a];
-                o[(5 * a + 2) * pl] = h2;
-                o[(5 * a + 4) * pl] = h4;
+                if (WY && wall_seg && r == 1) c2[0] = ghost(c2[1], c2[2], c2[3]);
+                if (WY && wall_seg && r == K.ny - 2) c4[3] = ghost(c4[2], c4[1], c4[0]);
+                hy[a][0] = upd_pos(SYd, Qy[P][2 * a] + K.dwf[a], c2[0], c2[1], c2[2], c2[3]);
+                hy[a][1] = upd_neg(SYd, Qy[P][2 * a + 1] + K.dwf[a], c4[0], c4[1], c4[2], c4[3]);
             }
+            // y part of row r is final: one contiguous 32 B block per node
+            const BufRes rs = row_res(fout, row_bytes, outr ? wrap_y(r) : 0, outr);
+            buf_store2(rs, vy_st, dvec2{hy[0][0], hy[0][1]});
+            buf_store2(rs, vy_st + 16u, dvec2{hy[1][0], hy[1][1]});
         }
 
         // ---- ring pushes ----
@@ -371,38 +396,55 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             ub_prev[q] = ub[q];
-            if (needB) uf_prev[q] = uf[q];
+            uf_prev[q] = needB ? uf[q] : uf_prev[q];   // a select: a conditional store here lands in scratch
         }
     };
 
-    for (int k = kbeg; k <= kend; k += 4) {
+    // the first group is peeled so that the loop is entered with the same
+    // memory operations in flight as on its back edge
+    body(std::integral_constant<int, 0>{}, kbeg);
+    body(std::integral_constant<int, 1>{}, kbeg + 1);
+    body(std::integral_constant<int, 2>{}, kbeg + 2);
+    body(std::integral_constant<int, 3>{}, kbeg + 3);
+    for (int k = kbeg + 4; k <= kpad; k += 4) {
         body(std::integral_constant<int, 0>{}, k);
-        if (k + 1 <= kend) body(std::integral_constant<int, 1>{}, k + 1);
-        if (k + 2 <= kend) body(std::integral_constant<int, 2>{}, k + 2);
-        if (k + 3 <= kend) body(std::integral_constant<int, 3>{}, k + 3);
+        body(std::integral_constant<int, 1>{}, k + 1);
+        body(std::integral_constant<int, 2>{}, k + 2);
+        body(std::integral_constant<int, 3>{}, k + 3);
     }
 }
 
-template <int TW, bool PLW>
+template <int TW, bool PLW, int PF, bool UNI>
 hipError_t launch_tw(const StepConsts& K, const FusedGrid& G, const double* fin, double* fout, hipStream_t s)
 {
     const dim3 grid(G.chunk * 8), block(TW);
     if (K.bcx && K.bcy)
-        hipLaunchKernelGGL((k_fused<TW, true, true, PLW>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, true, true, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
     else if (K.bcx)
-        hipLaunchKernelGGL((k_fused<TW, true, false, PLW>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, true, false, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
     else if (K.bcy)
-        hipLaunchKernelGGL((k_fused<TW, false, true, PLW>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, false, true, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
     else
-        hipLaunchKernelGGL((k_fused<TW, false, false, PLW>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, false, false, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
     return hipGetLastError();
 }
 
-template <int TW>
+template <int TW, int PF>
 hipError_t launch_pl(const StepConsts& K, const FusedGrid& G, const double* fin, double* fout, hipStream_t s)
 {
-    if (K.pl == PL_NEWTON) return launch_tw<TW, false>(K, G, fin, fout, s);
-    return launch_tw<TW, true>(K, G, fin, fout, s);
+    if (K.pl == PL_NEWTON) {
+        if (K.uniform) return launch_tw<TW, false, PF, true>(K, G, fin, fout, s);
+        return launch_tw<TW, false, PF, false>(K, G, fin, fout, s);
+    }
+    if (K.uniform) return launch_tw<TW, true, PF, true>(K, G, fin, fout, s);
+    return launch_tw<TW, true, PF, false>(K, G, fin, fout, s);
+}
+
+template <int TW>
+hipError_t launch_pf(const StepConsts& K, int pf, const FusedGrid& G, const double* fin, double* fout, hipStream_t s)
+{
+    if (pf <= 2) return launch_pl<TW, 2>(K, G, fin, fout, s);
+    return launch_pl<TW, 3>(K, G, fin, fout, s);
 }
 
 }  // namespace
@@ -410,7 +452,7 @@ hipError_t launch_pl(const StepConsts& K, const FusedGrid& G, const double* fin,
 bool fused_shape_ok(const StepConsts& K, FusedShape sh)
 {
     (void)K;
-    return (sh.tile_w == 64 || sh.tile_w == 128 || sh.tile_w == 256) && sh.seg_h >= 1;
+    return (sh.tile_w == 64 || sh.tile_w == 128) && sh.seg_h >= 1 && sh.prefetch >= 2 && sh.prefetch <= 3;
 }
 
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s)
@@ -422,9 +464,8 @@ hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, d
     const int total = G.nstrips * G.nsegs;
     G.chunk = (total + 7) / 8;
     switch (sh.tile_w) {
-    case 64: return launch_pl<64>(K, G, fin, fout, s);
-    case 128: return launch_pl<128>(K, G, fin, fout, s);
-    case 256: return launch_pl<256>(K, G, fin, fout, s);
+    case 64: return launch_pf<64>(K, sh.prefetch, G, fin, fout, s);
+    case 128: return launch_pf<128>(K, sh.prefetch, G, fin, fout, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -25,8 +25,11 @@ hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp,
 struct FusedShape {
     int tile_w;    // lanes per workgroup (multiple of 64, 64..1024)
     int seg_h;     // rows per segment
+    int prefetch;  // rows loaded ahead of the one being collided (2 or 3)
 };
 bool fused_shape_ok(const StepConsts& K, FusedShape sh);
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s);
+// Same step with one wave per velocity component (64-column strips; tile_w unused).
+hipError_t launch_fused2(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s);
 
 }  // namespace mdf

@@ -75,8 +75,8 @@ class Solver:
     def steps(self) -> int:
         return L.mdf_steps(self.ctx)
 
-    def set_kernel(self, variant: int, tile_w: int = 0, seg_h: int = 0):
-        L.mdf_set_kernel(self.ctx, variant, tile_w, seg_h)
+    def set_kernel(self, variant: int, tile_w: int = 0, seg_h: int = 0, prefetch: int = 0):
+        L.mdf_set_kernel(self.ctx, variant, tile_w, seg_h, prefetch)
         return self
 
     def step(self, n: int = 1):

@@ -74,7 +74,7 @@ def test_null_context_calls(L):
     assert lib.mdf_step(None, 1) == L.MDF_EINVAL
     assert lib.mdf_moments(None, None, None, None) == L.MDF_EINVAL
     assert lib.mdf_derived(None, None, 1) == L.MDF_EINVAL
-    assert lib.mdf_set_kernel(None, 1, 0, 0) == L.MDF_EINVAL
+    assert lib.mdf_set_kernel(None, 1, 0, 0, 0) == L.MDF_EINVAL
     assert lib.mdf_dt(None) == 0.0 and lib.mdf_steps(None) == 0
     lib.mdf_destroy(None)
 

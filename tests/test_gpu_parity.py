@@ -138,46 +138,46 @@ def _compare(key, Solver, variant, shape=(0, 0)):
     return o
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (0, 0)), (1, (64, 8)), (1, (128, 5)), (1, (256, 64))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 8, 2)), (1, (128, 5, 3)), (2, (0, 0)), (2, (0, 64, 2)), (2, (0, 3, 3))])
 def test_taylor_green_64_1000_steps(gpu, variant, shape):
     """The 64^2 Taylor-Green configuration: 1000 FP64 steps agree with the oracle to 1e-12."""
     _compare("tg64", gpu, variant, shape)
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 7)), (1, (128, 3)), (1, (64, 1))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 7)), (1, (128, 3)), (2, (0, 1)), (2, (0, 7, 3))])
 def test_ragged_periodic(gpu, variant, shape):
     """80 x 52 periodic grid: several strips, a ragged last strip, segments of 1-7 rows."""
     _compare("ragged", gpu, variant, shape)
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (0, 0)), (1, (64, 9))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 9)), (2, (0, 0)), (2, (0, 9, 3))])
 def test_cavity_128_1000_steps(gpu, variant, shape):
     """Lid-driven cavity (the 1024^2 configuration at 128^2): walls on all sides, lid 0.1."""
     _compare("cavity128", gpu, variant, shape)
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 5)), (1, (128, 48))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 5)), (2, (0, 5)), (2, (0, 48, 3))])
 def test_cavity_with_interior_field(gpu, variant, shape):
     _compare("cavity_field48", gpu, variant, shape)
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 6)), (1, (256, 32))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 6)), (2, (0, 6)), (2, (0, 32, 3))])
 def test_poiseuille_walls_in_y(gpu, variant, shape):
     _compare("poiseuille32", gpu, variant, shape)
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 6)), (1, (128, 13))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 6)), (2, (0, 6)), (2, (0, 13, 3))])
 def test_walls_in_x_periodic_y(gpu, variant, shape):
     _compare("wallx40", gpu, variant, shape)
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 10))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 10)), (2, (0, 10)), (2, (0, 4, 3))])
 def test_mapped_periodic_grid(gpu, variant, shape):
     _compare("mapped64", gpu, variant, shape)
 
 
 @pytest.mark.parametrize("pl_n", [0.5, 1.5])
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 8))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 8)), (2, (0, 8)), (2, (0, 5, 3))])
 def test_powerlaw_stretched_cavity(gpu, pl_n, variant, shape):
     """Power-law cavity on the tanh-stretched grid (the 2048^2 configuration at 64^2)."""
     _compare(f"plcav_n{pl_n}", gpu, variant, shape)
