@@ -119,8 +119,9 @@ mdf_status mdf_save(mdf_ctx* ctx, double* f);
 mdf_status mdf_load(mdf_ctx* ctx, const double* f);
 
 /* Kernel selection for the time step: variant 0 = three-pass reference path,
- * 1 = fused single-pass strip kernel with one wave per strip, 2 = fused
- * single-pass strip kernel with one wave per velocity component (default).
+ * 1 = fused single-pass strip kernel with one wave per strip (default for a
+ * power-law fluid), 2 = fused single-pass strip kernel with one wave per
+ * velocity component (default for a Newtonian fluid).
  * tile_w (columns per strip incl. the 8-column halo; 64 or 128; variant 1
  * only), seg_h (rows per segment, >= 1) and prefetch (rows loaded ahead,
  * 2 or 3) apply to the fused variants; 0 keeps the current value.  Results

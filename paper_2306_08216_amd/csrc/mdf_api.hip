@@ -162,20 +162,22 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     return K;
 }
 
-mdf::FusedShape default_shape(const mdf_params& p)
+mdf::FusedShape default_shape(const mdf_params& p, int cus)
 {
-    // One wave per strip (64 columns, 56 outputs) and enough row segments for
-    // about 4096 workgroups: the step is latency bound at one wave per SIMD,
-    // so many short segments beat fewer tall ones down to about 8 rows.
+    // One round of workgroups: both fused variants hold four workgroups per
+    // compute unit (one 64-lane strip wave per SIMD, or two set waves per strip
+    // at two waves per SIMD), so cus*4 strip segments run at once.  Taking as
+    // few segments as fill that round keeps the 8 halo rows each segment
+    // recomputes to a minimum; a second, partial round would idle most SIMDs.
     mdf::FusedShape sh;
     sh.tile_w = 64;
     sh.prefetch = 2;
+    const int slots = 4 * (cus > 0 ? cus : 256);
     const int nstrips = (p.nx + sh.tile_w - 9) / (sh.tile_w - 8);
-    int nseg = 4096 / (nstrips > 0 ? nstrips : 1);
+    int nseg = slots / (nstrips > 0 ? nstrips : 1);
     if (nseg < 1) nseg = 1;
     int h = (p.ny + nseg - 1) / nseg;
     if (h < 8) h = 8;
-    if (h > 64) h = 64;
     sh.seg_h = h;
     return sh;
 }
@@ -223,7 +225,14 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     c->K = make_consts(*p, L);
     c->K.gx = c->gx;
     c->K.gy = c->gy;
-    c->shape = default_shape(*p);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
+    c->shape = default_shape(*p, cus);
+    // one wave per velocity component fits two waves per SIMD for a Newtonian
+    // fluid; the power-law viscosity solve needs more registers than that
+    // allows, and there one wave per strip is faster
+    c->variant = p->pl_n == 1.0 ? 2 : 1;
 
     // derivative scales 1/(X' dxi) per node (uniform: 1/dx)
     std::string hbuf;

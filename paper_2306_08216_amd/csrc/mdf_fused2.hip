@@ -153,22 +153,12 @@ __device__ __forceinline__ void relax5(const double* phi, const double* e, Relax
     o[4] = e[4] + (r.kp * g4 - dy);
 }
 
+// The march of one strip segment: output columns xs0..xs1-1, rows ys0..ys1-1.
 template <bool WX, bool WY, bool PLW, int PF, bool UNI>
-__global__ __launch_bounds__(2 * TW2) void k_fused2(StepConsts K, const double* __restrict__ fin,
-                                                    double* __restrict__ fout, Grid2 G)
+__device__ __forceinline__ void fused2_march(const StepConsts& K, const double* __restrict__ fin,
+                                             double* __restrict__ fout, int xs0, int xs1, int ys0, int ys1,
+                                             double (*mom)[4][2][TW2], double (*xch)[2][5][TW2])
 {
-    __shared__ double mom[2][4][2][TW2];   // [collision][quantity][set][lane]
-    __shared__ double xch[2][2][5][TW2];   // [exchange][set][j1 j3 u v P][lane]
-
-    // XCD-aware order: consecutive segments of a strip land on the same XCD
-    const int L = (int)(blockIdx.x % 8) * G.chunk + (int)(blockIdx.x / 8);
-    if (L >= G.nstrips * G.nsegs) return;
-    const int strip = L / G.nsegs, seg = L - strip * G.nsegs;
-    const int xs0 = (int)((unsigned)(strip * K.nx) / (unsigned)G.nstrips);
-    const int xs1 = (int)((unsigned)((strip + 1) * K.nx) / (unsigned)G.nstrips);
-    const int ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
-    const int ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
-
     const int lane = threadIdx.x & (TW2 - 1);
     const int a = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // own set, uniform per wave
     const int x = xs0 - 4 + lane;
@@ -419,6 +409,36 @@ __global__ __launch_bounds__(2 * TW2) void k_fused2(StepConsts K, const double* 
         body(std::integral_constant<int, 2>{}, k + 2);
         body(std::integral_constant<int, 3>{}, k + 3);
     }
+}
+
+template <bool WX, bool WY, bool PLW, int PF, bool UNI>
+__global__ __launch_bounds__(2 * TW2) void k_fused2(StepConsts K, const double* __restrict__ fin,
+                                                    double* __restrict__ fout, Grid2 G)
+{
+    __shared__ double mom[2][4][2][TW2];   // [collision][quantity][set][lane]
+    __shared__ double xch[2][2][5][TW2];   // [exchange][set][j1 j3 u v P][lane]
+
+    // XCD-aware order: consecutive segments of a strip land on the same XCD
+    const int L = (int)(blockIdx.x % 8) * G.chunk + (int)(blockIdx.x / 8);
+    if (L >= G.nstrips * G.nsegs) return;
+    const int strip = L / G.nsegs, seg = L - strip * G.nsegs;
+    const int xs0 = (int)((unsigned)(strip * K.nx) / (unsigned)G.nstrips);
+    const int xs1 = (int)((unsigned)((strip + 1) * K.nx) / (unsigned)G.nstrips);
+    const int ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
+    const int ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
+
+    if constexpr (WX || WY) {
+        // a segment whose march stays more than 4 nodes away from every wall
+        // meets no wall rule, ghost node or wrap: the wall-free march computes
+        // exactly the same values with less code
+        const bool near_x = WX && (xs0 <= 8 || xs1 >= K.nx - 8);
+        const bool near_y = WY && (ys0 <= 8 || ys1 >= K.ny - 8);
+        if (!near_x && !near_y) {
+            fused2_march<false, false, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, mom, xch);
+            return;
+        }
+    }
+    fused2_march<WX, WY, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, mom, xch);
 }
 
 template <bool PLW, int PF, bool UNI>

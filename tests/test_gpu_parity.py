@@ -101,6 +101,20 @@ def _plcav(pl_n):
     return prob
 
 
+def _stretched_cavity(n, pl_n):
+    """Cavity on the tanh-stretched grid, wide enough for segments that touch
+    no wall (the kernels run those through their wall-free march)."""
+    if pl_n == 1.0:
+        prob = P.cavity(n, re=1000.0)
+        _, g, dxm = P.tanh_mapping(n, 1.5)
+        prob.inv_dx_x, prob.inv_dx_y, prob.dx_min = g, g.copy(), dxm
+    else:
+        prob = P.powerlaw_cavity(n, pl_n=pl_n)
+    u, v, p = _wall_field(n, seed=13, amp=0.03)
+    prob.u0, prob.v0, prob.p0 = u, v, p
+    return prob
+
+
 CASES = {
     "tg64": lambda: (P.taylor_green(64, u0=0.01, nu=0.01), 1000),
     "ragged": lambda: (_ragged(), 200),
@@ -111,6 +125,8 @@ CASES = {
     "mapped64": lambda: (_mapped(), 200),
     "plcav_n0.5": lambda: (_plcav(0.5), 200),
     "plcav_n1.5": lambda: (_plcav(1.5), 200),
+    "stretched144": lambda: (_stretched_cavity(144, 1.0), 100),
+    "plstretched144": lambda: (_stretched_cavity(144, 0.5), 100),
 }
 
 
@@ -181,6 +197,14 @@ def test_mapped_periodic_grid(gpu, variant, shape):
 def test_powerlaw_stretched_cavity(gpu, pl_n, variant, shape):
     """Power-law cavity on the tanh-stretched grid (the 2048^2 configuration at 64^2)."""
     _compare(f"plcav_n{pl_n}", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("key", ["stretched144", "plstretched144"])
+@pytest.mark.parametrize("variant,shape", [(1, (64, 10)), (2, (0, 10)), (2, (0, 17, 3))])
+def test_stretched_cavity_interior_segments(gpu, key, variant, shape):
+    """Mapped-grid cavities (Newtonian and power law) with segments away from
+    every wall next to segments that meet the walls."""
+    _compare(key, gpu, variant, shape)
 
 
 @pytest.mark.parametrize("key", ["tg64", "cavity128", "plcav_n0.5", "plcav_n1.5"])
