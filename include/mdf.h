@@ -123,10 +123,24 @@ mdf_status mdf_load(mdf_ctx* ctx, const double* f);
  * power-law fluid), 2 = fused single-pass strip kernel with one wave per
  * velocity component (default for a Newtonian fluid).
  * tile_w (columns per strip incl. the 8-column halo; 64 or 128; variant 1
- * only), seg_h (rows per segment, >= 1) and prefetch (rows loaded ahead,
- * 2 or 3) apply to the fused variants; 0 keeps the current value.  Results
- * agree to rounding whatever the choice. */
+ * only), seg_h and prefetch (rows loaded ahead, 2 or 3) apply to the fused
+ * variants; 0 keeps the current value.  seg_h > 0 cuts every strip into
+ * segments of seg_h rows; seg_h < 0 (the default) selects the balanced
+ * partition: one round of workgroups on the device, with fewer rows in the
+ * segments next to walls, whose rows cost more.  Changing the variant or the
+ * shape rebuilds that partition (a short synchronous upload on the context's
+ * stream).  Results agree to rounding whatever the choice. */
 mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t seg_h, int32_t prefetch);
+
+/* Host-only preview of the balanced partition the fused variant (1 or 2)
+ * uses for these parameters with `slots` workgroups per round (the library
+ * takes 4 per compute unit): writes (strip, first row, end row) triples to
+ * out[3*i..3*i+2], strips being the tile_w-8 column slices of the grid
+ * (tile_w 64 or 128 for variant 1; variant 2 always uses 64), and returns the
+ * number of segments, or 0 for invalid input or when cap is too small.  No
+ * device work. */
+int32_t mdf_plan_segments(const mdf_params* p, int32_t variant, int32_t tile_w, int32_t slots, int32_t* out,
+                          int32_t cap);
 
 double      mdf_dt(const mdf_ctx* ctx);          /* time step, or 0 for NULL       */
 int64_t     mdf_steps(const mdf_ctx* ctx);       /* steps taken since mdf_init     */

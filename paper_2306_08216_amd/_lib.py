@@ -46,6 +46,8 @@ SIGNATURES = {
     "mdf_save": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mdf_load": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mdf_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "mdf_plan_segments": (C.c_int32, [C.POINTER(mdf_params), C.c_int32, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_int32), C.c_int32]),
     "mdf_dt": (C.c_double, [C.c_void_p]),
     "mdf_steps": (C.c_int64, [C.c_void_p]),
     "mdf_last_error": (C.c_char_p, [C.c_void_p]),
@@ -125,6 +127,13 @@ def mdf_load(ctx: int, f: int):
 
 def mdf_set_kernel(ctx: int, variant: int, tile_w: int = 0, seg_h: int = 0, prefetch: int = 0):
     return check(lib().mdf_set_kernel(ctx, int(variant), int(tile_w), int(seg_h), int(prefetch)), ctx)
+
+
+def mdf_plan_segments(p: mdf_params, variant: int, tile_w: int, slots: int, cap: int = 8192):
+    """(strip, ys0, ys1) rows of the balanced partition, as a list of tuples."""
+    buf = (C.c_int32 * (3 * cap))()
+    n = lib().mdf_plan_segments(C.byref(p), int(variant), int(tile_w), int(slots), buf, int(cap))
+    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n)]
 
 
 def mdf_dt(ctx: int) -> float:

@@ -29,7 +29,9 @@ struct mdf_ctx {
     int cur = 0;
     int64_t steps = 0;
     int variant = 2;
-    mdf::FusedShape shape{64, 8, 2};
+    mdf::FusedShape shape{64, -1, 2, nullptr, 0};
+    int4* seg = nullptr;          // segment table of the balanced partition (device)
+    int slots = 1024;             // workgroups one round of the fused step holds
     StepConsts K;
     std::string err;
 };
@@ -58,10 +60,12 @@ mdf_status hip_check(mdf_ctx* c, hipError_t e, const char* what)
 
 struct Layout {
     size_t pitch;                 // nodes per row
-    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, total;  // bytes
+    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, off_seg, total;  // bytes
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+constexpr int kSegCap = 4096;   // entries of the segment table (one per workgroup)
 
 Layout layout_for(int nx, int ny)
 {
@@ -79,6 +83,7 @@ Layout layout_for(int nx, int ny)
     L.off_gy = o;   o += align256((size_t)ny * sizeof(double));
     L.off_dp = o;   o += align256(8 * 1024 * sizeof(double));
     L.off_do = o;   o += align256(8 * sizeof(double));
+    L.off_seg = o;  o += align256(kSegCap * sizeof(int4));
     L.total = o;
     return L;
 }
@@ -162,24 +167,114 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     return K;
 }
 
-mdf::FusedShape default_shape(const mdf_params& p, int cus)
+// Greedy segmentation of every strip at cost budget T (row units); returns
+// the number of segments, or -1 if some segment cannot hold a single row.
+int segment_strips(int nx, int ny, bool wall_x, bool wall_y, int nstrips, double cx, double cy, double T, int4* out,
+                   int cap)
 {
-    // One round of workgroups: both fused variants hold four workgroups per
-    // compute unit (one 64-lane strip wave per SIMD, or two set waves per strip
-    // at two waves per SIMD), so cus*4 strip segments run at once.  Taking as
-    // few segments as fill that round keeps the 8 halo rows each segment
-    // recomputes to a minimum; a second, partial round would idle most SIMDs.
-    mdf::FusedShape sh;
-    sh.tile_w = 64;
-    sh.prefetch = 2;
-    const int slots = 4 * (cus > 0 ? cus : 256);
-    const int nstrips = (p.nx + sh.tile_w - 9) / (sh.tile_w - 8);
-    int nseg = slots / (nstrips > 0 ? nstrips : 1);
-    if (nseg < 1) nseg = 1;
-    int h = (p.ny + nseg - 1) / nseg;
-    if (h < 8) h = 8;
-    sh.seg_h = h;
+    int n = 0;
+    for (int s = 0; s < nstrips; ++s) {
+        // the strip bounds and wall tests the fused kernels use
+        const int xs0 = (int)((unsigned)(s * nx) / (unsigned)nstrips);
+        const int xs1 = (int)((unsigned)((s + 1) * nx) / (unsigned)nstrips);
+        const double fx = (wall_x && (xs0 <= 8 || xs1 >= nx - 8)) ? cx : 1.0;
+        int y = 0;
+        while (y < ny) {
+            double f = fx * ((wall_y && y <= 8) ? cy : 1.0);
+            int h = (int)std::floor(T / f) - 8;
+            if (wall_y && y + h >= ny - 8) h = (int)std::floor(T / (fx * cy)) - 8;   // ends next to the top wall
+            if (h < 1) return -1;
+            if (y + h > ny) h = ny - y;
+            if (out && n < cap) out[n] = make_int4(s, y, y + h, 0);
+            ++n;
+            y += h;
+        }
+    }
+    return n;
+}
+
+}  // namespace
+
+namespace mdf {
+
+int balanced_partition(int nx, int ny, bool wall_x, bool wall_y, int tile_w, int slots, double cx, double cy,
+                       int4* out, int cap)
+{
+    const int nstrips = (nx + tile_w - 9) / (tile_w - 8);
+    const double fmax = cx * cy;
+    double lo = 9.0, hi = fmax * (ny + 8) + 1.0;   // hi: one segment per strip always fits
+    if (segment_strips(nx, ny, wall_x, wall_y, nstrips, cx, cy, hi, nullptr, 0) > slots) {
+        lo = hi;   // more strips than slots: one segment each
+    } else {
+        while (hi - lo > 0.25) {
+            const double mid = 0.5 * (lo + hi);
+            const int n = segment_strips(nx, ny, wall_x, wall_y, nstrips, cx, cy, mid, nullptr, 0);
+            if (n > 0 && n <= slots)
+                hi = mid;
+            else
+                lo = mid;
+        }
+        lo = hi;
+    }
+    const int n = segment_strips(nx, ny, wall_x, wall_y, nstrips, cx, cy, lo, out, cap);
+    return (n > 0 && n <= cap) ? n : 0;
+}
+
+}  // namespace mdf
+
+namespace {
+
+mdf::FusedShape default_shape()
+{
+    // One wave per strip of 64 columns (56 outputs), rows from the balanced table.
+    mdf::FusedShape sh{64, -1, 2, nullptr, 0};
     return sh;
+}
+
+// Relative cost per row of a segment next to an x wall (cx) and next to a y
+// wall (cy), measured on MI355X for each fused kernel against its wall-free
+// march (lid-driven cavity 1024^2): the wall rule, the ghost nodes and the
+// divergent lanes of the x-wall strips make those rows dearer.
+void segment_costs(int variant, double& cx, double& cy)
+{
+    if (variant == 1) {
+        cx = 1.53;
+        cy = 1.19;
+    } else {
+        cx = 1.19;
+        cy = 1.08;
+    }
+}
+
+// Build and upload the balanced segment table when the shape asks for it.
+mdf_status prepare_shape(mdf_ctx* c)
+{
+    mdf::FusedShape& sh = c->shape;
+    if (c->variant == 0 || sh.seg_h > 0) {
+        sh.table = nullptr;
+        sh.nwg = 0;
+        return MDF_OK;
+    }
+    double cx, cy;
+    segment_costs(c->variant, cx, cy);
+    int4* host = new (std::nothrow) int4[kSegCap];
+    if (!host) return fail(c, MDF_EDEVICE, "out of host memory");
+    const int slots = c->slots < kSegCap ? c->slots : kSegCap;
+    // the per-component kernel always runs 64-lane strips
+    const int tw = c->variant == 2 ? 64 : sh.tile_w;
+    const int n = mdf::balanced_partition(c->p.nx, c->p.ny, c->p.bc_x == MDF_BC_WALL, c->p.bc_y == MDF_BC_WALL, tw,
+                                          slots, cx, cy, host, kSegCap);
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = hipMemcpyAsync(c->seg, host, sizeof(int4) * n, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    delete[] host;
+    if (n <= 0) return fail(c, MDF_EINVAL, "grid too wide for the segment table");
+    if (e != hipSuccess) return hip_check(c, e, "segment table upload");
+    sh.table = c->seg;
+    sh.nwg = n;
+    return MDF_OK;
 }
 
 bool check_ctx(mdf_ctx* c) { return c != nullptr; }
@@ -222,13 +317,16 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     c->gy = (double*)(c->ws + L.off_gy);
     c->diag_part = (double*)(c->ws + L.off_dp);
     c->diag_out = (double*)(c->ws + L.off_do);
+    c->seg = (int4*)(c->ws + L.off_seg);
     c->K = make_consts(*p, L);
     c->K.gx = c->gx;
     c->K.gy = c->gy;
+    // both fused kernels hold four workgroups per compute unit
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 0;
-    c->shape = default_shape(*p, cus);
+    c->slots = 4 * (cus > 0 ? cus : 256);
+    c->shape = default_shape();
     // one wave per velocity component fits two waves per SIMD for a Newtonian
     // fluid; the power-law viscosity solve needs more registers than that
     // allows, and there one wave per strip is faster
@@ -259,6 +357,13 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
         delete[] gxh;
         if (e != hipSuccess) {
             mdf_status s = hip_check(nullptr, e, "metric upload");
+            delete c;
+            return s;
+        }
+    }
+    {
+        const mdf_status s = prepare_shape(c);
+        if (s != MDF_OK) {
             delete c;
             return s;
         }
@@ -348,13 +453,43 @@ mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t s
     if (variant < 0 || variant > 2) return fail(c, MDF_EINVAL, "variant must be 0, 1 or 2");
     mdf::FusedShape sh = c->shape;
     if (tile_w) sh.tile_w = tile_w;
-    if (seg_h) sh.seg_h = seg_h;
+    if (seg_h) sh.seg_h = seg_h < 0 ? -1 : seg_h;
     if (prefetch) sh.prefetch = prefetch;
     if (!mdf::fused_shape_ok(c->K, sh))
-        return fail(c, MDF_EINVAL, "tile_w must be 64 or 128, seg_h >= 1 and prefetch 2 or 3");
+        return fail(c, MDF_EINVAL, "tile_w must be 64 or 128 and prefetch 2 or 3");
+    const int old_variant = c->variant;
+    const mdf::FusedShape old_shape = c->shape;
     c->variant = variant;
     c->shape = sh;
-    return MDF_OK;
+    const mdf_status s = prepare_shape(c);
+    if (s != MDF_OK) {
+        c->variant = old_variant;
+        c->shape = old_shape;
+    }
+    return s;
+}
+
+int32_t mdf_plan_segments(const mdf_params* p, int32_t variant, int32_t tile_w, int32_t slots, int32_t* out,
+                          int32_t cap)
+{
+    if (validate(p)) return 0;
+    if (variant != 1 && variant != 2) return 0;
+    if (variant == 2) tile_w = 64;
+    if (tile_w != 64 && tile_w != 128) return 0;
+    if (slots < 1 || cap < 1 || !out) return 0;
+    double cx, cy;
+    segment_costs(variant, cx, cy);
+    int4* host = new (std::nothrow) int4[cap];
+    if (!host) return 0;
+    const int n = mdf::balanced_partition(p->nx, p->ny, p->bc_x == MDF_BC_WALL, p->bc_y == MDF_BC_WALL, tile_w, slots,
+                                          cx, cy, host, cap);
+    for (int i = 0; i < n; ++i) {
+        out[3 * i + 0] = host[i].x;
+        out[3 * i + 1] = host[i].y;
+        out[3 * i + 2] = host[i].z;
+    }
+    delete[] host;
+    return n;
 }
 
 double mdf_dt(const mdf_ctx* c) { return c ? c->K.dt : 0.0; }

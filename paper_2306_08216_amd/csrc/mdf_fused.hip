@@ -28,7 +28,8 @@ namespace mdf {
 namespace {
 
 struct FusedGrid {
-    int nstrips, nsegs, chunk;
+    int nstrips, nsegs, chunk, nwg;
+    const int4* table;   // (strip, ys0, ys1, 0) per workgroup, or null: nsegs equal segments per strip
 };
 
 // equilibrium component (velocity along the wall normal axis) used by the wall
@@ -59,6 +60,10 @@ __device__ __forceinline__ int lclamp(int l)
 // Read the x-neighbours (offsets -2..2) of the 4 exchanged components; at
 // x-walls replace the wall column by the wall rule and the column beyond it
 // by the ghost node.  comp c = (alpha = c/2, j = 1 if c even else 3).
+// X = [4 components][their non-equilibrium parts g = f - f^eq][P][lane]: the
+// wall rule f_w = f^eq_w + 2 g(n1) - g(n2) then needs no equilibrium of the
+// neighbours, only f^eq at the wall (u = v = 0, P = P(n1)): +-kf P for the u
+// set and 0 for the v set along x.
 template <int TW, bool WX>
 __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW], int lane, int x, double nb[4][5],
                                              bool wall_strip)
@@ -70,11 +75,11 @@ __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW
     if (WX && wall_strip) {
         if (x >= 1 && x <= 2) {
             const int l1 = lclamp<TW>(lane + (1 - x)), l2 = lclamp<TW>(lane + (2 - x));
-            const double m1[3] = {X[4][l1], X[5][l1], X[6][l1]};
-            const double m2[3] = {X[4][l2], X[5][l2], X[6][l2]};
+            const double kp = K.kf * X[8][l1];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double w0 = wall_comp(K, c >> 1, 0, (c & 1) ? -1.0 : 1.0, X[c][l1], X[c][l2], m1, m2, 0.0);
+                const double ew = c >= 2 ? 0.0 : ((c & 1) ? -kp : kp);
+                const double w0 = ew + 2.0 * X[4 + c][l1] - X[4 + c][l2];
                 if (x == 1) {
                     nb[c][1] = w0;
                     nb[c][0] = ghost(w0, X[c][l1], X[c][l2]);
@@ -85,11 +90,11 @@ __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW
         }
         if (x >= K.nx - 3 && x <= K.nx - 2) {
             const int l1 = lclamp<TW>(lane + (K.nx - 2 - x)), l2 = lclamp<TW>(lane + (K.nx - 3 - x));
-            const double m1[3] = {X[4][l1], X[5][l1], X[6][l1]};
-            const double m2[3] = {X[4][l2], X[5][l2], X[6][l2]};
+            const double kp = K.kf * X[8][l1];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double w0 = wall_comp(K, c >> 1, 0, (c & 1) ? -1.0 : 1.0, X[c][l1], X[c][l2], m1, m2, 0.0);
+                const double ew = c >= 2 ? 0.0 : ((c & 1) ? -kp : kp);
+                const double w0 = ew + 2.0 * X[4 + c][l1] - X[4 + c][l2];
                 if (x == K.nx - 2) {
                     nb[c][3] = w0;
                     nb[c][4] = ghost(w0, X[c][l1], X[c][l2]);
@@ -105,7 +110,7 @@ __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW
 template <int TW, bool WX, bool WY, bool PLW, int PF, bool UNI>
 __device__ __forceinline__ void fused_march(const StepConsts& K, const double* __restrict__ fin,
                                             double* __restrict__ fout, int xs0, int xs1, int ys0, int ys1,
-                                            double (*xs)[7][TW])
+                                            double (*xs)[9][TW])
 {
     const int lane = threadIdx.x;
     const int x = xs0 - 4 + lane;
@@ -194,7 +199,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
         load_row(k + PF, pre[(P + PF) & 3]);
 
         // ---- A: Step (1) on row k ----
-        double fbp[10], fhp[10], ub[3];
+        double fbp[10], fhp[10], ub[3], gb[4];
         {
             double fe[10];
             node_moments(cur, K.c, ub[0], ub[1], ub[2]);
@@ -202,6 +207,10 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
             Relax ra, rb;
             step1_factors_t<PLW ? PL_HALF : PL_NEWTON>(K, cur, fe, ra, rb);
             relax(cur, fe, rb, fbp);
+            gb[0] = fbp[1] - fe[1];
+            gb[1] = fbp[3] - fe[3];
+            gb[2] = fbp[6] - fe[6];
+            gb[3] = fbp[8] - fe[8];
             if (k >= ys0 && k < ys1) {
                 relax(cur, fe, ra, fhp);
             } else {
@@ -244,9 +253,9 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
             X[2][lane] = fbp[6];
             X[3][lane] = fbp[8];
             if (WX && wall_strip) {
-                X[4][lane] = ub[0];
-                X[5][lane] = ub[1];
-                X[6][lane] = ub[2];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) X[4 + c][lane] = gb[c];
+                X[8][lane] = ub[2];
             }
             exchange_barrier<TW / 64>();
             double nb[4][5];
@@ -265,6 +274,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
         const bool needB = (m >= ys0 - 2) && (m < ys1 + 2) && (WY ? (m >= 1 && m <= K.ny - 2) : true);
         double f2c[2] = {0.0, 0.0};
         double fm[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, uf[3] = {0.0, 0.0, 0.0};
+        double gf[4] = {0.0, 0.0, 0.0, 0.0};
         if (needB) {
             const Stencil SYh = y_stencil_h(wrap_y(m));
             double fb[10];
@@ -285,6 +295,10 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
             equilibrium(uf[0], uf[1], uf[2], K, fe);
             const Relax rq = step3_factors_t<PLW ? PL_HALF : PL_NEWTON>(K, fb, fe);
             relax(fb, fe, rq, fm);
+            gf[0] = fm[1] - fe[1];
+            gf[1] = fm[3] - fe[3];
+            gf[2] = fm[6] - fe[6];
+            gf[3] = fm[8] - fe[8];
             F4[S2][0] = fm[4];
             F4[S2][1] = fm[9];
             f2c[0] = fm[2];
@@ -323,9 +337,9 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
             X[2][lane] = fm[6];
             X[3][lane] = fm[8];
             if (WX && wall_strip) {
-                X[4][lane] = uf[0];
-                X[5][lane] = uf[1];
-                X[6][lane] = uf[2];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) X[4 + c][lane] = gf[c];
+                X[8][lane] = uf[2];
             }
             exchange_barrier<TW / 64>();
             double nb[4][5];
@@ -408,17 +422,26 @@ template <int TW, bool WX, bool WY, bool PLW, int PF, bool UNI>
 __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __restrict__ fin, double* __restrict__ fout,
                                               FusedGrid G)
 {
-    __shared__ double xs[2][7][TW];
+    __shared__ double xs[2][9][TW];
 
     // XCD-aware order: consecutive segments of a strip land on the same XCD
     const int L = (int)(blockIdx.x % 8) * G.chunk + (int)(blockIdx.x / 8);
-    if (L >= G.nstrips * G.nsegs) return;
-    const int strip = L / G.nsegs, seg = L - strip * G.nsegs;
-    // balanced partitions (products stay below 2^31 for any grid the ABI accepts)
+    if (L >= G.nwg) return;
+    int strip, ys0, ys1;
+    if (G.table) {
+        const int4 d = G.table[L];
+        strip = d.x;
+        ys0 = d.y;
+        ys1 = d.z;
+    } else {
+        // equal segments (products stay below 2^31 for any grid the ABI accepts)
+        strip = L / G.nsegs;
+        const int seg = L - strip * G.nsegs;
+        ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
+        ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
+    }
     const int xs0 = (int)((unsigned)(strip * K.nx) / (unsigned)G.nstrips);
     const int xs1 = (int)((unsigned)((strip + 1) * K.nx) / (unsigned)G.nstrips);
-    const int ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
-    const int ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
 
     if constexpr (WX || WY) {
         // A segment whose march (columns xs0-4..xs1+3, rows ys0-4..ys1+3) stays
@@ -474,7 +497,7 @@ hipError_t launch_pf(const StepConsts& K, int pf, const FusedGrid& G, const doub
 bool fused_shape_ok(const StepConsts& K, FusedShape sh)
 {
     (void)K;
-    return (sh.tile_w == 64 || sh.tile_w == 128) && sh.seg_h >= 1 && sh.prefetch >= 2 && sh.prefetch <= 3;
+    return (sh.tile_w == 64 || sh.tile_w == 128) && sh.prefetch >= 2 && sh.prefetch <= 3;
 }
 
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s)
@@ -482,9 +505,17 @@ hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, d
     FusedGrid G;
     const int wout = sh.tile_w - 8;
     G.nstrips = (K.nx + wout - 1) / wout;
-    G.nsegs = (K.ny + sh.seg_h - 1) / sh.seg_h;
-    const int total = G.nstrips * G.nsegs;
-    G.chunk = (total + 7) / 8;
+    if (sh.seg_h > 0) {
+        G.nsegs = (K.ny + sh.seg_h - 1) / sh.seg_h;
+        G.nwg = G.nstrips * G.nsegs;
+        G.table = nullptr;
+    } else {
+        if (!sh.table || sh.nwg <= 0) return hipErrorInvalidValue;
+        G.nsegs = 0;
+        G.nwg = sh.nwg;
+        G.table = sh.table;
+    }
+    G.chunk = (G.nwg + 7) / 8;
     switch (sh.tile_w) {
     case 64: return launch_pf<64>(K, sh.prefetch, G, fin, fout, s);
     case 128: return launch_pf<128>(K, sh.prefetch, G, fin, fout, s);

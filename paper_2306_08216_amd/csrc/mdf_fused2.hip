@@ -35,7 +35,8 @@ namespace {
 constexpr int TW2 = 64;   // lanes (columns) per strip, 56 output columns
 
 struct Grid2 {
-    int nstrips, nsegs, chunk;
+    int nstrips, nsegs, chunk, nwg;
+    const int4* table;   // (strip, ys0, ys1, 0) per workgroup, or null: nsegs equal segments per strip
 };
 
 // equilibrium component j of set a at the moments (u, v, P) (eq. 2.2.5)
@@ -61,8 +62,10 @@ __device__ __forceinline__ double wall_j(const StepConsts& K, int a, int j, doub
 __device__ __forceinline__ int lc(int l) { return l < 0 ? 0 : (l >= TW2 ? TW2 - 1 : l); }
 
 // x-neighbours (offsets -2..2) of the two exchanged components (j = 1, 3) of
-// set a from X = [j1, j3, u, v, P][lane]; at x walls the wall column takes the
-// wall rule and the column beyond it the ghost node.
+// set a from X = [j1, j3, g1, g3, P][lane] with g = f - f^eq; at x walls the
+// wall column takes the wall rule f_w = f^eq_w + 2 g(n1) - g(n2), where f^eq at
+// the wall (u = v = 0, P = P(n1)) is +-kf P for the u set and 0 for the v
+// set, and the column beyond it the ghost node.
 template <bool WX>
 __device__ __forceinline__ void x_nb(const StepConsts& K, const double (*X)[TW2], int a, int lane, int x,
                                      double nb[2][5], bool wall_strip)
@@ -74,11 +77,10 @@ __device__ __forceinline__ void x_nb(const StepConsts& K, const double (*X)[TW2]
     if (WX && wall_strip) {
         if (x >= 1 && x <= 2) {
             const int l1 = lc(lane + (1 - x)), l2 = lc(lane + (2 - x));
-            const double m1[3] = {X[2][l1], X[3][l1], X[4][l1]};
-            const double m2[3] = {X[2][l2], X[3][l2], X[4][l2]};
+            const double kp = a == 0 ? K.kf * X[4][l1] : 0.0;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const double w0 = wall_j(K, a, c == 0 ? 1 : 3, X[c][l1], X[c][l2], m1, m2, 0.0);
+                const double w0 = (c == 0 ? kp : -kp) + 2.0 * X[2 + c][l1] - X[2 + c][l2];
                 if (x == 1) {
                     nb[c][1] = w0;
                     nb[c][0] = ghost(w0, X[c][l1], X[c][l2]);
@@ -89,11 +91,10 @@ __device__ __forceinline__ void x_nb(const StepConsts& K, const double (*X)[TW2]
         }
         if (x >= K.nx - 3 && x <= K.nx - 2) {
             const int l1 = lc(lane + (K.nx - 2 - x)), l2 = lc(lane + (K.nx - 3 - x));
-            const double m1[3] = {X[2][l1], X[3][l1], X[4][l1]};
-            const double m2[3] = {X[2][l2], X[3][l2], X[4][l2]};
+            const double kp = a == 0 ? K.kf * X[4][l1] : 0.0;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const double w0 = wall_j(K, a, c == 0 ? 1 : 3, X[c][l1], X[c][l2], m1, m2, 0.0);
+                const double w0 = (c == 0 ? kp : -kp) + 2.0 * X[2 + c][l1] - X[2 + c][l2];
                 if (x == K.nx - 2) {
                     nb[c][3] = w0;
                     nb[c][4] = ghost(w0, X[c][l1], X[c][l2]);
@@ -242,7 +243,7 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
         load_row(k + PF, pre[(P + PF) & 3]);
 
         // ---- A: Step (1) on row k ----
-        double fbp[5], fhp[5], ub[3];
+        double fbp[5], fhp[5], ub[3], gb[2];
         {
             double e[5], gam;
             collide_moments<PLW>(K, mom[0], a, lane, cur, ub, e, gam);
@@ -258,6 +259,8 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
                 rb = Relax{K.b_s, K.b_p};
             }
             relax5(cur, e, rb, fbp);
+            gb[0] = fbp[1] - e[1];
+            gb[1] = fbp[3] - e[3];
             if (k >= ys0 && k < ys1) {
                 relax5(cur, e, ra, fhp);
             } else {
@@ -289,8 +292,8 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
             X[0][lane] = fbp[1];
             X[1][lane] = fbp[3];
             if (WX && wall_strip) {
-                X[2][lane] = ub[0];
-                X[3][lane] = ub[1];
+                X[2][lane] = gb[0];
+                X[3][lane] = gb[1];
                 X[4][lane] = ub[2];
             }
             lds_barrier();
@@ -305,7 +308,7 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
         const int m = k - 2;
         const bool needB = (m >= ys0 - 2) && (m < ys1 + 2) && (WY ? (m >= 1 && m <= K.ny - 2) : true);
         double f2c = 0.0;
-        double fm[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, uf[3] = {0.0, 0.0, 0.0};
+        double fm[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, uf[3] = {0.0, 0.0, 0.0}, gf[2] = {0.0, 0.0};
         if (needB) {
             const Stencil SYh = y_stencil_h(wrap_y(m));
             double a2[4] = {W2[P], W2[S3], W2[S2], W2[S1]};   // rows m-2 .. m+1
@@ -329,6 +332,8 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
                 rq = Relax{K.q_s, K.q_p};
             }
             relax5(fb, e, rq, fm);
+            gf[0] = fm[1] - e[1];
+            gf[1] = fm[3] - e[3];
             F4[S2] = fm[4];
             f2c = fm[2];
         }
@@ -354,8 +359,8 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
             X[0][lane] = fm[1];
             X[1][lane] = fm[3];
             if (WX && wall_strip) {
-                X[2][lane] = uf[0];
-                X[3][lane] = uf[1];
+                X[2][lane] = gf[0];
+                X[3][lane] = gf[1];
                 X[4][lane] = uf[2];
             }
             lds_barrier();
@@ -416,16 +421,25 @@ __global__ __launch_bounds__(2 * TW2) void k_fused2(StepConsts K, const double* 
                                                     double* __restrict__ fout, Grid2 G)
 {
     __shared__ double mom[2][4][2][TW2];   // [collision][quantity][set][lane]
-    __shared__ double xch[2][2][5][TW2];   // [exchange][set][j1 j3 u v P][lane]
+    __shared__ double xch[2][2][5][TW2];   // [exchange][set][j1 j3 g1 g3 P][lane]
 
     // XCD-aware order: consecutive segments of a strip land on the same XCD
     const int L = (int)(blockIdx.x % 8) * G.chunk + (int)(blockIdx.x / 8);
-    if (L >= G.nstrips * G.nsegs) return;
-    const int strip = L / G.nsegs, seg = L - strip * G.nsegs;
+    if (L >= G.nwg) return;
+    int strip, ys0, ys1;
+    if (G.table) {
+        const int4 d = G.table[L];
+        strip = d.x;
+        ys0 = d.y;
+        ys1 = d.z;
+    } else {
+        strip = L / G.nsegs;
+        const int seg = L - strip * G.nsegs;
+        ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
+        ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
+    }
     const int xs0 = (int)((unsigned)(strip * K.nx) / (unsigned)G.nstrips);
     const int xs1 = (int)((unsigned)((strip + 1) * K.nx) / (unsigned)G.nstrips);
-    const int ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
-    const int ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
 
     if constexpr (WX || WY) {
         // a segment whose march stays more than 4 nodes away from every wall
@@ -474,9 +488,17 @@ hipError_t launch_fused2(const StepConsts& K, FusedShape sh, const double* fin, 
     Grid2 G;
     const int wout = TW2 - 8;
     G.nstrips = (K.nx + wout - 1) / wout;
-    G.nsegs = (K.ny + sh.seg_h - 1) / sh.seg_h;
-    const int total = G.nstrips * G.nsegs;
-    G.chunk = (total + 7) / 8;
+    if (sh.seg_h > 0) {
+        G.nsegs = (K.ny + sh.seg_h - 1) / sh.seg_h;
+        G.nwg = G.nstrips * G.nsegs;
+        G.table = nullptr;
+    } else {
+        if (!sh.table || sh.nwg <= 0) return hipErrorInvalidValue;
+        G.nsegs = 0;
+        G.nwg = sh.nwg;
+        G.table = sh.table;
+    }
+    G.chunk = (G.nwg + 7) / 8;
     if (sh.prefetch <= 2) return launch_pf2<2>(K, G, fin, fout, s);
     return launch_pf2<3>(K, G, fin, fout, s);
 }

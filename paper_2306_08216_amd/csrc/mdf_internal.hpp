@@ -21,12 +21,24 @@ hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp,
                              hipStream_t s);
 
 // Fused single-pass step: strips of tile_w lanes (one column each, 8 halo
-// columns) marching over row segments of seg_h rows.
+// columns) marching over row segments.  Segments are either seg_h rows each
+// (seg_h > 0) or taken from a device table of (strip, ys0, ys1, 0) entries,
+// one per workgroup, that balances the cost of wall and interior segments.
 struct FusedShape {
-    int tile_w;    // lanes per workgroup (multiple of 64, 64..1024)
-    int seg_h;     // rows per segment
-    int prefetch;  // rows loaded ahead of the one being collided (2 or 3)
+    int tile_w;          // lanes per workgroup (multiple of 64, 64..1024)
+    int seg_h;           // rows per segment, or <= 0 for the table
+    int prefetch;        // rows loaded ahead of the one being collided (2 or 3)
+    const int4* table;   // device segment table (used when seg_h <= 0)
+    int nwg;             // entries of the table
 };
+
+// Partition of the strips into segments so that the costliest segment is as
+// cheap as possible with at most `slots` segments.  A segment of h rows costs
+// f * (h + 8) row units (8 halo rows are recomputed), f = cx on strips next
+// to an x wall, times cy on segments next to a y wall.  Returns the number of
+// entries written to out (capacity cap), or 0 if cap is too small.
+int balanced_partition(int nx, int ny, bool wall_x, bool wall_y, int tile_w, int slots, double cx, double cy,
+                       int4* out, int cap);
 bool fused_shape_ok(const StepConsts& K, FusedShape sh);
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s);
 // Same step with one wave per velocity component (64-column strips; tile_w unused).

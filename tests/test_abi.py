@@ -85,3 +85,39 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+@pytest.mark.parametrize("n,bc,variant,tile_w", [(1024, 1, 2, 64), (1024, 1, 1, 64), (2048, 1, 1, 64),
+                                                 (1024, 0, 2, 64), (100, 1, 1, 128), (37, 0, 1, 64),
+                                                 (4099, 1, 2, 64), (2048, 1, 1, 128)])
+def test_balanced_partition_covers_every_row_once(L, n, bc, variant, tile_w):
+    """The launch plan of the fused step: every (strip, row) exactly once, at
+    most one round of workgroups, and wall segments no taller than interior
+    ones (their rows cost more)."""
+    p, keep = _params(L, nx=n, ny=n + 3, bc_x=bc, bc_y=bc)
+    slots = 1024
+    segs = L.mdf_plan_segments(p, variant, tile_w, slots)
+    assert segs
+    tw = 64 if variant == 2 else tile_w
+    nstrips = -(-n // (tw - 8))
+    assert len(segs) <= max(slots, nstrips)
+    cover = {}
+    for s, y0, y1 in segs:
+        assert 0 <= s < nstrips and 0 <= y0 < y1 <= n + 3
+        cover.setdefault(s, []).append((y0, y1))
+    assert sorted(cover) == list(range(nstrips))
+    for s, iv in cover.items():
+        iv.sort()
+        assert iv[0][0] == 0 and iv[-1][1] == n + 3
+        assert all(a[1] == b[0] for a, b in zip(iv, iv[1:]))   # contiguous, no overlap
+    if bc and nstrips > 2 and n >= 1024:
+        h_int = max(y1 - y0 for s, y0, y1 in segs if 0 < s < nstrips - 1)
+        h_wall = max(y1 - y0 for s, y0, y1 in segs if s == 0)
+        assert h_wall < h_int
+
+
+def test_plan_rejects_bad_arguments(L):
+    p, keep = _params(L)
+    assert L.mdf_plan_segments(p, 0, 64, 1024) == []
+    assert L.mdf_plan_segments(p, 1, 96, 1024) == []
+    assert L.mdf_plan_segments(p, 1, 64, 0) == []
