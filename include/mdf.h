@@ -36,6 +36,7 @@ extern "C" {
 #endif
 
 typedef struct mdf_ctx mdf_ctx;
+typedef struct mdf_batch mdf_batch;
 
 typedef enum {
     MDF_OK = 0,
@@ -146,6 +147,63 @@ double      mdf_dt(const mdf_ctx* ctx);          /* time step, or 0 for NULL    
 int64_t     mdf_steps(const mdf_ctx* ctx);       /* steps taken since mdf_init     */
 const char* mdf_last_error(const mdf_ctx* ctx);  /* never NULL; "" when none       */
 void        mdf_destroy(mdf_ctx* ctx);           /* synchronises; NULL is a no-op  */
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent instances of the same method advanced together
+ * (a project addition, not in the paper).  Each instance has its own grid
+ * size, viscosity and therefore its own time step dt = CFL dx / c (eq. 3.1)
+ * and relaxation rates (Sec. 2.2); one mdf_batch_step advances every instance
+ * by one of its own steps with ONE kernel launch covering all instances.  All
+ * instances must be periodic on both axes, on uniform grids, and share pl_n.
+ *
+ * The caller owns the workspace (device, 256-byte aligned, at least
+ * mdf_batch_workspace_size bytes) and keeps it alive until
+ * mdf_batch_destroy; it holds the per-instance constants, the launch plan,
+ * two state buffers and a backup buffer for the autotuner.  The library
+ * creates one private stream and two events per batch (for graph replay). */
+
+/* Bytes of workspace for `count` instances ps[0..count-1]; 0 if invalid. */
+size_t mdf_batch_workspace_size(const mdf_params* ps, int32_t count);
+
+/* u0s[i], v0s[i], p0s[i]: host arrays of DEVICE pointers to instance i's
+ * initial fields (ny_i*nx_i doubles, x fastest), read before return.
+ * Synchronises.  On error *out is NULL and nothing needs freeing. */
+mdf_status mdf_batch_init(const mdf_params* ps, int32_t count, const double* const* u0s, const double* const* v0s,
+                          const double* const* p0s, void* workspace, size_t ws_bytes, void* hip_stream,
+                          mdf_batch** out);
+
+/* n steps of every instance, one launch per step, asynchronous on the
+ * batch's stream. */
+mdf_status mdf_batch_step(mdf_batch* b, int64_t n);
+
+/* The same n steps replayed from a captured HIP graph (captured on first use
+ * for this n and starting buffer, then reused).  The replay runs on the
+ * batch's private stream, ordered after earlier work on the batch's stream and
+ * before later work on it.  Results are identical to mdf_batch_step. */
+mdf_status mdf_batch_step_graph(mdf_batch* b, int64_t n);
+
+/* Kernel for the batch: variant 1 (one wave per strip) or 2 (one wave per
+ * velocity component), prefetch 2 or 3 rows, and `rounds` (1..8) rounds of
+ * workgroups in the balanced partition.  Rebuilds the plan (synchronous). */
+mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t prefetch, int32_t rounds);
+
+/* Autotuner: times each candidate kernel (variant, prefetch, rounds) over
+ * `steps` steps on the batch itself, restores the state and step count
+ * afterwards, selects the fastest and writes it to choice[0..2] (may be
+ * NULL).  Synchronises.  Results do not depend on the choice (to rounding). */
+mdf_status mdf_batch_autotune(mdf_batch* b, int32_t steps, int32_t* choice);
+
+/* Instance i's moments (DEVICE planes of ny_i*nx_i doubles, NULL skips a
+ * plane) and dense state copy (DEVICE, 10*ny_i*nx_i doubles, same order as
+ * mdf_save); asynchronous on the batch's stream. */
+mdf_status mdf_batch_moments(mdf_batch* b, int32_t i, double* u, double* v, double* p);
+mdf_status mdf_batch_save(mdf_batch* b, int32_t i, double* f);
+
+double      mdf_batch_dt(const mdf_batch* b, int32_t i);   /* instance time step, 0 if invalid */
+int64_t     mdf_batch_steps(const mdf_batch* b);          /* steps since mdf_batch_init       */
+int32_t     mdf_batch_workgroups(const mdf_batch* b);     /* workgroups of one step launch    */
+const char* mdf_batch_last_error(const mdf_batch* b);     /* never NULL                       */
+void        mdf_batch_destroy(mdf_batch* b);               /* synchronises; NULL is a no-op    */
 
 #ifdef __cplusplus
 }

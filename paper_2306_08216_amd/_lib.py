@@ -52,6 +52,21 @@ SIGNATURES = {
     "mdf_steps": (C.c_int64, [C.c_void_p]),
     "mdf_last_error": (C.c_char_p, [C.c_void_p]),
     "mdf_destroy": (None, [C.c_void_p]),
+    "mdf_batch_workspace_size": (C.c_size_t, [C.POINTER(mdf_params), C.c_int32]),
+    "mdf_batch_init": (C.c_int, [C.POINTER(mdf_params), C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                 C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p,
+                                 C.POINTER(C.c_void_p)]),
+    "mdf_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "mdf_batch_step_graph": (C.c_int, [C.c_void_p, C.c_int64]),
+    "mdf_batch_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "mdf_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "mdf_batch_moments": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mdf_batch_save": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "mdf_batch_dt": (C.c_double, [C.c_void_p, C.c_int32]),
+    "mdf_batch_steps": (C.c_int64, [C.c_void_p]),
+    "mdf_batch_workgroups": (C.c_int32, [C.c_void_p]),
+    "mdf_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "mdf_batch_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -151,3 +166,71 @@ def mdf_last_error(ctx) -> str:
 
 def mdf_destroy(ctx: int):
     lib().mdf_destroy(ctx)
+
+
+# batches ---------------------------------------------------------------------
+
+def bcheck(status: int, b=None):
+    if status != MDF_OK:
+        msg = lib().mdf_batch_last_error(b)
+        raise MdfError(status, msg.decode() if msg else "")
+    return status
+
+
+def mdf_batch_workspace_size(ps, count: int) -> int:
+    return lib().mdf_batch_workspace_size(ps, int(count))
+
+
+def mdf_batch_init(ps, count: int, u0s, v0s, p0s, workspace: int, ws_bytes: int, stream: int) -> int:
+    arr = C.c_void_p * count
+    out = C.c_void_p()
+    bcheck(lib().mdf_batch_init(ps, int(count), arr(*u0s), arr(*v0s), arr(*p0s), workspace, ws_bytes, stream,
+                                C.byref(out)))
+    return out.value
+
+
+def mdf_batch_step(b: int, n: int):
+    return bcheck(lib().mdf_batch_step(b, int(n)), b)
+
+
+def mdf_batch_step_graph(b: int, n: int):
+    return bcheck(lib().mdf_batch_step_graph(b, int(n)), b)
+
+
+def mdf_batch_set_kernel(b: int, variant: int, prefetch: int, rounds: int):
+    return bcheck(lib().mdf_batch_set_kernel(b, int(variant), int(prefetch), int(rounds)), b)
+
+
+def mdf_batch_autotune(b: int, steps: int):
+    choice = (C.c_int32 * 3)()
+    bcheck(lib().mdf_batch_autotune(b, int(steps), choice), b)
+    return tuple(choice)
+
+
+def mdf_batch_moments(b: int, i: int, u: int, v: int, p: int):
+    return bcheck(lib().mdf_batch_moments(b, int(i), u, v, p), b)
+
+
+def mdf_batch_save(b: int, i: int, f: int):
+    return bcheck(lib().mdf_batch_save(b, int(i), f), b)
+
+
+def mdf_batch_dt(b: int, i: int) -> float:
+    return lib().mdf_batch_dt(b, int(i))
+
+
+def mdf_batch_steps(b: int) -> int:
+    return lib().mdf_batch_steps(b)
+
+
+def mdf_batch_workgroups(b: int) -> int:
+    return lib().mdf_batch_workgroups(b)
+
+
+def mdf_batch_last_error(b) -> str:
+    s = lib().mdf_batch_last_error(b)
+    return s.decode() if s else ""
+
+
+def mdf_batch_destroy(b: int):
+    lib().mdf_batch_destroy(b)

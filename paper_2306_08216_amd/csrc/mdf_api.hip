@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/mdf.h"
 #include "mdf_internal.hpp"
@@ -167,27 +168,33 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     return K;
 }
 
-// Greedy segmentation of every strip at cost budget T (row units); returns
-// the number of segments, or -1 if some segment cannot hold a single row.
-int segment_strips(int nx, int ny, bool wall_x, bool wall_y, int nstrips, double cx, double cy, double T, int4* out,
+// Greedy segmentation of every strip of every grid at cost budget T (row
+// units); returns the number of segments, or -1 if some segment cannot hold a
+// single row.
+int segment_strips(const mdf::PlanGrid* grids, int count, int tile_w, double cx, double cy, double T, int4* out,
                    int cap)
 {
     int n = 0;
-    for (int s = 0; s < nstrips; ++s) {
-        // the strip bounds and wall tests the fused kernels use
-        const int xs0 = (int)((unsigned)(s * nx) / (unsigned)nstrips);
-        const int xs1 = (int)((unsigned)((s + 1) * nx) / (unsigned)nstrips);
-        const double fx = (wall_x && (xs0 <= 8 || xs1 >= nx - 8)) ? cx : 1.0;
-        int y = 0;
-        while (y < ny) {
-            double f = fx * ((wall_y && y <= 8) ? cy : 1.0);
-            int h = (int)std::floor(T / f) - 8;
-            if (wall_y && y + h >= ny - 8) h = (int)std::floor(T / (fx * cy)) - 8;   // ends next to the top wall
-            if (h < 1) return -1;
-            if (y + h > ny) h = ny - y;
-            if (out && n < cap) out[n] = make_int4(s, y, y + h, 0);
-            ++n;
-            y += h;
+    for (int g = 0; g < count; ++g) {
+        const int nx = grids[g].nx, ny = grids[g].ny;
+        const bool wall_x = grids[g].wall_x, wall_y = grids[g].wall_y;
+        const int nstrips = (nx + tile_w - 9) / (tile_w - 8);
+        for (int s = 0; s < nstrips; ++s) {
+            // the strip bounds and wall tests the fused kernels use
+            const int xs0 = (int)((unsigned)(s * nx) / (unsigned)nstrips);
+            const int xs1 = (int)((unsigned)((s + 1) * nx) / (unsigned)nstrips);
+            const double fx = (wall_x && (xs0 <= 8 || xs1 >= nx - 8)) ? cx : 1.0;
+            int y = 0;
+            while (y < ny) {
+                double f = fx * ((wall_y && y <= 8) ? cy : 1.0);
+                int h = (int)std::floor(T / f) - 8;
+                if (wall_y && y + h >= ny - 8) h = (int)std::floor(T / (fx * cy)) - 8;   // ends next to the top wall
+                if (h < 1) return -1;
+                if (y + h > ny) h = ny - y;
+                if (out && n < cap) out[n] = make_int4(s, y, y + h, g);
+                ++n;
+                y += h;
+            }
         }
     }
     return n;
@@ -197,18 +204,19 @@ int segment_strips(int nx, int ny, bool wall_x, bool wall_y, int nstrips, double
 
 namespace mdf {
 
-int balanced_partition(int nx, int ny, bool wall_x, bool wall_y, int tile_w, int slots, double cx, double cy,
-                       int4* out, int cap)
+int balanced_partition_multi(const PlanGrid* grids, int count, int tile_w, int slots, double cx, double cy, int4* out,
+                             int cap)
 {
-    const int nstrips = (nx + tile_w - 9) / (tile_w - 8);
+    int maxny = 0;
+    for (int g = 0; g < count; ++g) maxny = grids[g].ny > maxny ? grids[g].ny : maxny;
     const double fmax = cx * cy;
-    double lo = 9.0, hi = fmax * (ny + 8) + 1.0;   // hi: one segment per strip always fits
-    if (segment_strips(nx, ny, wall_x, wall_y, nstrips, cx, cy, hi, nullptr, 0) > slots) {
+    double lo = 9.0, hi = fmax * (maxny + 8) + 1.0;   // hi: one segment per strip always fits
+    if (segment_strips(grids, count, tile_w, cx, cy, hi, nullptr, 0) > slots) {
         lo = hi;   // more strips than slots: one segment each
     } else {
         while (hi - lo > 0.25) {
             const double mid = 0.5 * (lo + hi);
-            const int n = segment_strips(nx, ny, wall_x, wall_y, nstrips, cx, cy, mid, nullptr, 0);
+            const int n = segment_strips(grids, count, tile_w, cx, cy, mid, nullptr, 0);
             if (n > 0 && n <= slots)
                 hi = mid;
             else
@@ -216,8 +224,15 @@ int balanced_partition(int nx, int ny, bool wall_x, bool wall_y, int tile_w, int
         }
         lo = hi;
     }
-    const int n = segment_strips(nx, ny, wall_x, wall_y, nstrips, cx, cy, lo, out, cap);
+    const int n = segment_strips(grids, count, tile_w, cx, cy, lo, out, cap);
     return (n > 0 && n <= cap) ? n : 0;
+}
+
+int balanced_partition(int nx, int ny, bool wall_x, bool wall_y, int tile_w, int slots, double cx, double cy,
+                       int4* out, int cap)
+{
+    const PlanGrid g{nx, ny, wall_x, wall_y};
+    return balanced_partition_multi(&g, 1, tile_w, slots, cx, cy, out, cap);
 }
 
 }  // namespace mdf
@@ -281,7 +296,133 @@ bool check_ctx(mdf_ctx* c) { return c != nullptr; }
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Batches of independent periodic instances (one launch per step for all).
+
+struct mdf_batch {
+    int count = 0;
+    hipStream_t stream = nullptr;   // the caller's stream
+    hipStream_t gstream = nullptr;  // private stream the captured step graphs replay on
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    double* f[2] = {nullptr, nullptr};
+    double* backup = nullptr;       // copy of the state while the autotuner runs
+    size_t state_doubles = 0;       // doubles of one state buffer (all instances)
+    mdf::BatchInst* d_insts = nullptr;
+    int4* d_table = nullptr;
+    int table_cap = 0;
+    std::vector<mdf::BatchInst> insts;
+    bool powerlaw = false;
+    int variant = 2, prefetch = 2, rounds = 1, slots = 1024, nwg = 0;
+    int cur = 0;
+    int64_t steps = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // by starting buffer
+    int64_t gn[2] = {0, 0};
+    std::string err;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t off_insts, off_table, off_f0, off_f1, off_backup, total;
+    size_t state_doubles;
+    int table_cap;
+    std::vector<long long> offs;   // per instance, doubles
+    std::vector<int> pitch;
+};
+
+const char* validate_batch(const mdf_params* ps, int count)
+{
+    if (!ps) return "params is NULL";
+    if (count < 1 || count > 65536) return "count must lie in 1..65536";
+    for (int i = 0; i < count; ++i) {
+        if (const char* e = validate(&ps[i])) return e;
+        if (ps[i].bc_x != MDF_BC_PERIODIC || ps[i].bc_y != MDF_BC_PERIODIC)
+            return "batched instances must be periodic on both axes";
+        if (ps[i].inv_dx_x || ps[i].inv_dx_y) return "batched instances must use uniform grids";
+        if (ps[i].pl_n != ps[0].pl_n) return "batched instances must share the fluid model (pl_n)";
+    }
+    return nullptr;
+}
+
+BatchLayout batch_layout(const mdf_params* ps, int count)
+{
+    BatchLayout B;
+    long long nstrips = 0;
+    size_t o = 0;
+    B.offs.resize(count);
+    B.pitch.resize(count);
+    for (int i = 0; i < count; ++i) {
+        B.pitch[i] = (ps[i].nx + 15) & ~15;
+        B.offs[i] = (long long)(o / sizeof(double));
+        o += align256(10 * (size_t)B.pitch[i] * (size_t)ps[i].ny * sizeof(double));
+        nstrips += (ps[i].nx + 55) / 56;
+    }
+    B.state_doubles = o / sizeof(double);
+    const long long cap = nstrips + 64 > 16384 ? nstrips + 64 : 16384;
+    B.table_cap = (int)cap;
+    size_t t = 0;
+    B.off_insts = t;  t += align256((size_t)count * sizeof(mdf::BatchInst));
+    B.off_table = t;  t += align256((size_t)B.table_cap * sizeof(int4));
+    B.off_f0 = t;     t += o;
+    B.off_f1 = t;     t += o;
+    B.off_backup = t; t += o;
+    B.total = t;
+    return B;
+}
+
+mdf_status bfail(mdf_batch* b, mdf_status s, const char* msg)
+{
+    if (b) b->err = msg;
+    return fail(nullptr, s, "%s", msg);
+}
+
+mdf_status bhip(mdf_batch* b, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MDF_OK;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    return bfail(b, MDF_EDEVICE, buf);
+}
+
+void batch_drop_graphs(mdf_batch* b)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (b->gexec[i]) (void)hipGraphExecDestroy(b->gexec[i]);
+        b->gexec[i] = nullptr;
+        b->gn[i] = 0;
+    }
+}
+
+// Balanced partition of all instances' strips over rounds * slots workgroups.
+mdf_status batch_plan(mdf_batch* b)
+{
+    std::vector<mdf::PlanGrid> g(b->count);
+    for (int i = 0; i < b->count; ++i) g[i] = mdf::PlanGrid{b->insts[i].K.nx, b->insts[i].K.ny, false, false};
+    std::vector<int4> host(b->table_cap);
+    const int n = mdf::balanced_partition_multi(g.data(), b->count, 64, b->slots * b->rounds, 1.0, 1.0, host.data(),
+                                                b->table_cap);
+    if (n <= 0) return bfail(b, MDF_EINVAL, "batch too large for its segment table");
+    hipError_t e = hipMemcpyAsync(b->d_table, host.data(), sizeof(int4) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "batch segment table upload");
+    b->nwg = n;
+    batch_drop_graphs(b);
+    return MDF_OK;
+}
+
+hipError_t batch_launch(mdf_batch* b, const double* fin, double* fout, hipStream_t s)
+{
+    if (b->variant == 1)
+        return mdf::launch_fused_batch(b->d_insts, b->d_table, b->nwg, b->powerlaw, b->prefetch, fin, fout, s);
+    return mdf::launch_fused2_batch(b->d_insts, b->d_table, b->nwg, b->powerlaw, b->prefetch, fin, fout, s);
+}
+
+}  // namespace
+
 extern "C" {
+
 
 size_t mdf_workspace_size(const mdf_params* p)
 {
@@ -507,6 +648,256 @@ void mdf_destroy(mdf_ctx* c)
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     delete c;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+size_t mdf_batch_workspace_size(const mdf_params* ps, int32_t count)
+{
+    if (validate_batch(ps, count)) return 0;
+    return batch_layout(ps, count).total;
+}
+
+mdf_status mdf_batch_init(const mdf_params* ps, int32_t count, const double* const* u0s, const double* const* v0s,
+                          const double* const* p0s, void* workspace, size_t ws_bytes, void* hip_stream,
+                          mdf_batch** out)
+{
+    if (!out) return fail(nullptr, MDF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (const char* e = validate_batch(ps, count)) return fail(nullptr, MDF_EINVAL, "%s", e);
+    if (!u0s || !v0s || !p0s) return fail(nullptr, MDF_EINVAL, "initial field arrays are NULL");
+    for (int i = 0; i < count; ++i)
+        if (!u0s[i] || !v0s[i] || !p0s[i]) return fail(nullptr, MDF_EINVAL, "initial fields of instance %d are NULL", i);
+    const BatchLayout B = batch_layout(ps, count);
+    if (!workspace) return fail(nullptr, MDF_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, MDF_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < B.total) return fail(nullptr, MDF_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, B.total);
+
+    mdf_batch* b = new (std::nothrow) mdf_batch;
+    if (!b) return fail(nullptr, MDF_EDEVICE, "out of host memory");
+    b->count = count;
+    b->stream = (hipStream_t)hip_stream;
+    b->ws = (char*)workspace;
+    b->ws_bytes = ws_bytes;
+    b->d_insts = (mdf::BatchInst*)(b->ws + B.off_insts);
+    b->d_table = (int4*)(b->ws + B.off_table);
+    b->table_cap = B.table_cap;
+    b->f[0] = (double*)(b->ws + B.off_f0);
+    b->f[1] = (double*)(b->ws + B.off_f1);
+    b->backup = (double*)(b->ws + B.off_backup);
+    b->state_doubles = B.state_doubles;
+    b->powerlaw = ps[0].pl_n != 1.0;
+    b->variant = b->powerlaw ? 1 : 2;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
+    b->slots = 4 * (cus > 0 ? cus : 256);
+    b->insts.resize(count);
+    for (int i = 0; i < count; ++i) {
+        Layout L{};
+        L.pitch = (size_t)B.pitch[i];
+        mdf::BatchInst& I = b->insts[i];
+        I.K = make_consts(ps[i], L);
+        I.K.gx = nullptr;
+        I.K.gy = nullptr;
+        I.off = B.offs[i];
+        I.nstrips = (ps[i].nx + 55) / 56;
+        I.pad = 0;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_insts, b->insts.data(), sizeof(mdf::BatchInst) * count, hipMemcpyHostToDevice,
+                           b->stream);
+    for (int i = 0; i < count && e == hipSuccess; ++i)
+        e = mdf::launch_init(b->insts[i].K, u0s[i], v0s[i], p0s[i], b->f[0] + b->insts[i].off, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        const mdf_status s = bhip(nullptr, e, "batch initialisation");
+        mdf_batch_destroy(b);
+        return s;
+    }
+    const mdf_status s = batch_plan(b);
+    if (s != MDF_OK) {
+        mdf_batch_destroy(b);
+        return s;
+    }
+    *out = b;
+    return MDF_OK;
+}
+
+mdf_status mdf_batch_step(mdf_batch* b, int64_t n)
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (n < 0) return bfail(b, MDF_EINVAL, "n must be >= 0");
+    for (int64_t i = 0; i < n; ++i) {
+        const hipError_t e = batch_launch(b, b->f[b->cur], b->f[1 - b->cur], b->stream);
+        if (e != hipSuccess) return bhip(b, e, "batch step launch");
+        b->cur = 1 - b->cur;
+        b->steps += 1;
+    }
+    return MDF_OK;
+}
+
+mdf_status mdf_batch_step_graph(mdf_batch* b, int64_t n)
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (n < 1) return bfail(b, MDF_EINVAL, "n must be >= 1");
+    const int par = b->cur;
+    if (!b->gexec[par] || b->gn[par] != n) {
+        if (b->gexec[par]) (void)hipGraphExecDestroy(b->gexec[par]);
+        b->gexec[par] = nullptr;
+        hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return bhip(b, e, "graph capture begin");
+        int c = par;
+        hipError_t el = hipSuccess;
+        for (int64_t i = 0; i < n && el == hipSuccess; ++i) {
+            el = batch_launch(b, b->f[c], b->f[1 - c], b->gstream);
+            c = 1 - c;
+        }
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->gstream, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bhip(b, el != hipSuccess ? el : e, "graph capture");
+        }
+        e = hipGraphInstantiate(&b->gexec[par], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->gexec[par] = nullptr;
+            return bhip(b, e, "graph instantiate");
+        }
+        b->gn[par] = n;
+    }
+    // order the replay after the caller's stream and the caller's later work after it
+    hipError_t e = hipEventRecord(b->ev_in, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->gstream, b->ev_in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(b->gexec[par], b->gstream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->gstream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out, 0);
+    if (e != hipSuccess) return bhip(b, e, "graph replay");
+    b->cur = (int)(par ^ (n & 1));
+    b->steps += n;
+    return MDF_OK;
+}
+
+mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t prefetch, int32_t rounds)
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (variant != 1 && variant != 2) return bfail(b, MDF_EINVAL, "variant must be 1 or 2");
+    if (prefetch != 2 && prefetch != 3) return bfail(b, MDF_EINVAL, "prefetch must be 2 or 3");
+    if (rounds < 1 || rounds > 8) return bfail(b, MDF_EINVAL, "rounds must lie in 1..8");
+    const int ov = b->variant, op = b->prefetch, orr = b->rounds;
+    b->variant = variant;
+    b->prefetch = prefetch;
+    b->rounds = rounds;
+    const mdf_status s = batch_plan(b);
+    if (s != MDF_OK) {
+        b->variant = ov;
+        b->prefetch = op;
+        b->rounds = orr;
+        (void)batch_plan(b);
+    }
+    return s;
+}
+
+mdf_status mdf_batch_autotune(mdf_batch* b, int32_t steps, int32_t* choice)
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (steps < 1) return bfail(b, MDF_EINVAL, "steps must be >= 1");
+    const size_t bytes = b->state_doubles * sizeof(double);
+    const int cur0 = b->cur;
+    const int64_t steps0 = b->steps;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->backup, b->f[cur0], bytes, hipMemcpyDeviceToDevice, b->stream);
+    float best = 1e30f;
+    int bv = b->variant, bp = b->prefetch, br = b->rounds;
+    const int cand[8][3] = {{2, 2, 1}, {2, 3, 1}, {1, 2, 1}, {1, 3, 1}, {2, 2, 2}, {1, 2, 2}, {2, 2, 3}, {1, 2, 3}};
+    mdf_status launch = MDF_OK;
+    for (int c = 0; c < 8 && e == hipSuccess && launch == MDF_OK; ++c) {
+        if (cand[c][0] == 2 && b->powerlaw) continue;   // the per-component kernel spills for a power law
+        if (mdf_batch_set_kernel(b, cand[c][0], cand[c][1], cand[c][2]) != MDF_OK) continue;
+        launch = mdf_batch_step(b, 1);   // first launch of this kernel outside the timing
+        if (launch == MDF_OK) e = hipEventRecord(t0, b->stream);
+        if (launch == MDF_OK && e == hipSuccess) launch = mdf_batch_step(b, steps);
+        if (launch == MDF_OK && e == hipSuccess) e = hipEventRecord(t1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e == hipSuccess && ms < best) {
+            best = ms;
+            bv = cand[c][0];
+            bp = cand[c][1];
+            br = cand[c][2];
+        }
+        // back to the state the tuning started from
+        b->cur = cur0;
+        const hipError_t er = hipMemcpyAsync(b->f[cur0], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+        if (e == hipSuccess) e = er;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    b->cur = cur0;
+    b->steps = steps0;
+    if (e != hipSuccess) return bhip(b, e, "autotune");
+    if (launch != MDF_OK) return launch;
+    const mdf_status s = mdf_batch_set_kernel(b, bv, bp, br);
+    if (s == MDF_OK && choice) {
+        choice[0] = bv;
+        choice[1] = bp;
+        choice[2] = br;
+    }
+    return s;
+}
+
+mdf_status mdf_batch_moments(mdf_batch* b, int32_t i, double* u, double* v, double* p)
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (i < 0 || i >= b->count) return bfail(b, MDF_EINVAL, "instance index out of range");
+    if (!u && !v && !p) return MDF_OK;
+    const mdf::BatchInst& I = b->insts[i];
+    return bhip(b, mdf::launch_moments(I.K, b->f[b->cur] + I.off, u, v, p, b->stream), "batch moments launch");
+}
+
+mdf_status mdf_batch_save(mdf_batch* b, int32_t i, double* f)
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (i < 0 || i >= b->count) return bfail(b, MDF_EINVAL, "instance index out of range");
+    if (!f) return bfail(b, MDF_EINVAL, "f is NULL");
+    const mdf::BatchInst& I = b->insts[i];
+    return bhip(b, mdf::launch_pack(I.K, b->f[b->cur] + I.off, f, b->stream), "batch save launch");
+}
+
+double mdf_batch_dt(const mdf_batch* b, int32_t i)
+{
+    if (!b || i < 0 || i >= b->count) return 0.0;
+    return b->insts[i].K.dt;
+}
+
+int64_t mdf_batch_steps(const mdf_batch* b) { return b ? b->steps : 0; }
+
+int32_t mdf_batch_workgroups(const mdf_batch* b) { return b ? b->nwg : 0; }
+
+const char* mdf_batch_last_error(const mdf_batch* b)
+{
+    if (b) return b->err.c_str();
+    return g_err.c_str();
+}
+
+void mdf_batch_destroy(mdf_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+    batch_drop_graphs(b);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->gstream) (void)hipStreamDestroy(b->gstream);
+    delete b;
 }
 
 }  // extern "C"

@@ -458,6 +458,23 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
     fused_march<TW, WX, WY, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
 }
 
+// Batched step: table entry L = (strip, ys0, ys1, instance); every instance
+// is periodic on a uniform grid with its own constants and state offset.
+template <bool PLW, int PF>
+__global__ __launch_bounds__(64) void k_fused_batch(const BatchInst* __restrict__ insts, const int4* __restrict__ table,
+                                                    int nwg, int chunk, const double* __restrict__ fin,
+                                                    double* __restrict__ fout)
+{
+    __shared__ double xs[2][9][64];
+    const int L = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
+    if (L >= nwg) return;
+    const int4 d = table[L];
+    const BatchInst& I = insts[d.w];
+    const int xs0 = (int)((unsigned)(d.x * I.K.nx) / (unsigned)I.nstrips);
+    const int xs1 = (int)((unsigned)((d.x + 1) * I.K.nx) / (unsigned)I.nstrips);
+    fused_march<64, false, false, PLW, PF, true>(I.K, fin + I.off, fout + I.off, xs0, xs1, d.y, d.z, xs);
+}
+
 template <int TW, bool PLW, int PF, bool UNI>
 hipError_t launch_tw(const StepConsts& K, const FusedGrid& G, const double* fin, double* fout, hipStream_t s)
 {
@@ -498,6 +515,26 @@ bool fused_shape_ok(const StepConsts& K, FusedShape sh)
 {
     (void)K;
     return (sh.tile_w == 64 || sh.tile_w == 128) && sh.prefetch >= 2 && sh.prefetch <= 3;
+}
+
+hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
+                              const double* fin, double* fout, hipStream_t s)
+{
+    if (nwg <= 0) return hipErrorInvalidValue;
+    const int chunk = (nwg + 7) / 8;
+    const dim3 grid(chunk * 8), block(64);
+    if (powerlaw) {
+        if (prefetch <= 2)
+            hipLaunchKernelGGL((k_fused_batch<true, 2>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+        else
+            hipLaunchKernelGGL((k_fused_batch<true, 3>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+    } else {
+        if (prefetch <= 2)
+            hipLaunchKernelGGL((k_fused_batch<false, 2>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+        else
+            hipLaunchKernelGGL((k_fused_batch<false, 3>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s)

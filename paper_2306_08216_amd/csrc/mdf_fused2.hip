@@ -455,6 +455,24 @@ __global__ __launch_bounds__(2 * TW2) void k_fused2(StepConsts K, const double* 
     fused2_march<WX, WY, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, mom, xch);
 }
 
+// Batched step: table entry L = (strip, ys0, ys1, instance); every instance
+// is periodic on a uniform grid with its own constants and state offset.
+template <bool PLW, int PF>
+__global__ __launch_bounds__(2 * TW2) void k_fused2_batch(const BatchInst* __restrict__ insts,
+                                                          const int4* __restrict__ table, int nwg, int chunk,
+                                                          const double* __restrict__ fin, double* __restrict__ fout)
+{
+    __shared__ double mom[2][4][2][TW2];
+    __shared__ double xch[2][2][5][TW2];
+    const int L = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
+    if (L >= nwg) return;
+    const int4 d = table[L];
+    const BatchInst& I = insts[d.w];
+    const int xs0 = (int)((unsigned)(d.x * I.K.nx) / (unsigned)I.nstrips);
+    const int xs1 = (int)((unsigned)((d.x + 1) * I.K.nx) / (unsigned)I.nstrips);
+    fused2_march<false, false, PLW, PF, true>(I.K, fin + I.off, fout + I.off, xs0, xs1, d.y, d.z, mom, xch);
+}
+
 template <bool PLW, int PF, bool UNI>
 hipError_t launch_bc(const StepConsts& K, const Grid2& G, const double* fin, double* fout, hipStream_t s)
 {
@@ -482,6 +500,26 @@ hipError_t launch_pf2(const StepConsts& K, const Grid2& G, const double* fin, do
 }
 
 }  // namespace
+
+hipError_t launch_fused2_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
+                               const double* fin, double* fout, hipStream_t s)
+{
+    if (nwg <= 0) return hipErrorInvalidValue;
+    const int chunk = (nwg + 7) / 8;
+    const dim3 grid(chunk * 8), block(2 * TW2);
+    if (powerlaw) {
+        if (prefetch <= 2)
+            hipLaunchKernelGGL((k_fused2_batch<true, 2>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+        else
+            hipLaunchKernelGGL((k_fused2_batch<true, 3>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+    } else {
+        if (prefetch <= 2)
+            hipLaunchKernelGGL((k_fused2_batch<false, 2>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+        else
+            hipLaunchKernelGGL((k_fused2_batch<false, 3>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_fused2(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s)
 {

@@ -39,6 +39,31 @@ struct FusedShape {
 // entries written to out (capacity cap), or 0 if cap is too small.
 int balanced_partition(int nx, int ny, bool wall_x, bool wall_y, int tile_w, int slots, double cx, double cy,
                        int4* out, int cap);
+
+// The same over several independent grids (a batch): entries carry the grid
+// index in their fourth field.
+struct PlanGrid {
+    int nx, ny;
+    bool wall_x, wall_y;
+};
+int balanced_partition_multi(const PlanGrid* grids, int count, int tile_w, int slots, double cx, double cy, int4* out,
+                             int cap);
+
+// One instance of a batch, as the batched step kernels read it.
+struct BatchInst {
+    StepConsts K;
+    long long off;   // offset of the instance's state, in doubles, within each state buffer
+    int nstrips;     // 56-column strips of the instance
+    int pad;
+};
+
+// Batched fused step: every segment of every instance in one launch.  The
+// instances share the boundary type and fluid model (periodic, uniform grid);
+// table entries are (strip, ys0, ys1, instance).
+hipError_t launch_fused2_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
+                               const double* fin, double* fout, hipStream_t s);
+hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
+                              const double* fin, double* fout, hipStream_t s);
 bool fused_shape_ok(const StepConsts& K, FusedShape sh);
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s);
 // Same step with one wave per velocity component (64-column strips; tile_w unused).

@@ -121,3 +121,29 @@ def test_plan_rejects_bad_arguments(L):
     assert L.mdf_plan_segments(p, 0, 64, 1024) == []
     assert L.mdf_plan_segments(p, 1, 96, 1024) == []
     assert L.mdf_plan_segments(p, 1, 64, 0) == []
+
+
+def test_batch_validation_without_device_work(L):
+    from paper_2306_08216_amd import problems as P
+    from paper_2306_08216_amd.solver import params_of
+    keep = []
+    good = [params_of(P.taylor_green(n), keep) for n in (16, 40, 64)]
+    arr = (L.mdf_params * 3)(*good)
+    n = L.mdf_batch_workspace_size(arr, 3)
+    assert n >= 3 * sum(10 * ((m + 15) // 16 * 16) * m * 8 for m in (16, 40, 64))
+    assert L.mdf_batch_workspace_size(arr, 0) == 0
+    bad_wall = (L.mdf_params * 2)(good[0], params_of(P.cavity(32), keep))
+    assert L.mdf_batch_workspace_size(bad_wall, 2) == 0
+    mapped = P.taylor_green(32)
+    mapped.inv_dx_x, mapped.dx_min = np.ones(32), 0.1
+    assert L.mdf_batch_workspace_size((L.mdf_params * 2)(good[0], params_of(mapped, keep)), 2) == 0
+    pl = P.taylor_green(32)
+    pl.pl_n, pl.nu_min, pl.nu_max = 0.5, 1e-4, 1e-1
+    assert L.mdf_batch_workspace_size((L.mdf_params * 2)(good[0], params_of(pl, keep)), 2) == 0
+    out = C.c_void_p()
+    arrp = (C.c_void_p * 3)()
+    s = L.lib().mdf_batch_init(arr, 3, arrp, arrp, arrp, None, 0, None, C.byref(out))
+    assert s == L.MDF_EINVAL and out.value is None
+    assert L.lib().mdf_batch_step(None, 1) == L.MDF_EINVAL
+    assert L.lib().mdf_batch_set_kernel(None, 1, 2, 1) == L.MDF_EINVAL
+    L.lib().mdf_batch_destroy(None)

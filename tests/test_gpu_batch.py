@@ -1,0 +1,157 @@
+"""GPU parity of the batched step: one launch per step over many periodic
+instances of different size and viscosity, each compared with its own oracle
+run; graph replay against eager stepping; the autotuner leaves the state as
+it found it.  Bar: max |GPU - oracle| <= 1e-12 (FP64 state)."""
+import functools
+import json
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2306_08216_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_08216_amd.batch import BatchSolver
+    return BatchSolver
+
+
+def _mixed(count=10, seed=7):
+    """Ragged sizes (strip and tile tails), nu spread over two decades."""
+    rng = np.random.default_rng(seed)
+    sizes = [40, 57, 64, 96, 113, 130, 64, 88, 150, 71][:count]
+    probs = []
+    for i, n in enumerate(sizes):
+        nu = float(10 ** rng.uniform(-3, -1))
+        probs.append(P.random_vortex(n, 500 + i, nu, kmax=6, urms=0.03))
+    return probs
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_f(key, i, steps):
+    from oracle.orc import Oracle
+    probs = _mixed() if key == "mixed" else None
+    o = Oracle(probs[i])
+    o.step(steps)
+    return o.f()
+
+
+def test_batch_matches_each_instance_oracle(gpu):
+    probs = _mixed()
+    steps = 30
+    say(f"[gpu batch] mixed count={len(probs)} sizes={[p.nx for p in probs]} steps={steps}")
+    b = gpu(probs)
+    assert b.workgroups > 0
+    for i, p in enumerate(probs):
+        assert b.dt(i) == pytest.approx(p.cfl * (p.lx / p.nx) / p.c, rel=1e-15)
+    b.step(steps)
+    b.synchronize()
+    for i, p in enumerate(probs):
+        f = b.save(i).cpu().numpy()
+        err = np.abs(f - _oracle_f("mixed", i, steps)).max()
+        say(f"    instance {i} n={p.nx} nu={p.nu:.3g} max|df|={err:.3e}")
+        assert np.all(np.isfinite(f)) and err <= TOL
+    b.close()
+
+
+@pytest.mark.parametrize("variant,prefetch,rounds", [(1, 2, 1), (1, 3, 2), (2, 3, 1), (2, 2, 3)])
+def test_batch_kernel_choices_agree(gpu, variant, prefetch, rounds):
+    probs = _mixed()
+    steps = 30
+    say(f"[gpu batch] kernel variant={variant} prefetch={prefetch} rounds={rounds}")
+    b = gpu(probs).set_kernel(variant, prefetch, rounds)
+    b.step(steps)
+    for i in (0, 4, 8):
+        err = np.abs(b.save(i).cpu().numpy() - _oracle_f("mixed", i, steps)).max()
+        say(f"    instance {i} max|df|={err:.3e}")
+        assert err <= TOL
+    b.close()
+
+
+def test_graph_replays_match_eager(gpu):
+    """Replay the captured n-step graph several times, with eager work of the
+    program in between, and check every replay against eager stepping."""
+    import torch
+    probs = _mixed(6)
+    say("[gpu batch] graph replay vs eager, 4 replays of 5 steps (+1 odd replay)")
+    eager = gpu(probs)
+    graph = gpu(probs)
+    for rep in range(4):
+        eager.step(5)
+        graph.step_graph(5)
+        u, _, _ = graph.moments(0)            # eager work between replays
+        _ = (u * 2.0).sum().item()
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            a = eager.save(i).cpu().numpy()
+            g = graph.save(i).cpu().numpy()
+            assert np.array_equal(a, g), (rep, i)
+    eager.step(3)
+    graph.step_graph(3)                        # odd length: starts from the other buffer next time
+    graph.step_graph(3)
+    eager.step(3)
+    for i in range(len(probs)):
+        assert np.array_equal(eager.save(i).cpu().numpy(), graph.save(i).cpu().numpy())
+    assert graph.steps == eager.steps == 26
+    eager.close()
+    graph.close()
+
+
+def test_autotune_restores_state_and_caches(gpu, tmp_path):
+    probs = _mixed(6)
+    say("[gpu batch] autotune")
+    b = gpu(probs)
+    b.step(4)
+    before = [b.save(i).cpu().numpy() for i in range(len(probs))]
+    cache = str(tmp_path / "tune.json")
+    choice, cached = b.autotune(cache, steps=3)
+    assert not cached and choice[0] in (1, 2) and choice[1] in (2, 3) and 1 <= choice[2] <= 3
+    assert b.steps == 4
+    for i in range(len(probs)):
+        assert np.array_equal(before[i], b.save(i).cpu().numpy())
+    entry = json.load(open(cache))[b.signature()]
+    assert tuple(entry["choice"]) == tuple(choice)
+    choice2, cached2 = b.autotune(cache)
+    assert cached2 and tuple(choice2) == tuple(choice)
+    b.step(26)
+    for i in (0, 3, 5):
+        assert np.abs(b.save(i).cpu().numpy() - _oracle_f("mixed", i, 30)).max() <= TOL
+    b.close()
+
+
+def test_full_batch_config_sampled(gpu):
+    """256 instances (sizes 64..512, nu log-uniform in [1e-3, 1e-1], k^-3 fields,
+    seed 20230614) in one launch per step; 8 sampled instances vs the oracle."""
+    from oracle.orc import Oracle
+    inst = P.batch_instances(256, seed=20230614)
+    probs = [P.random_vortex(n, sd, nu) for n, nu, sd in inst]
+    steps = 3
+    say(f"[gpu batch] full config count=256 nodes={sum(p.nx * p.ny for p in probs)} steps={steps}")
+    b = gpu(probs)
+    b.step(steps)
+    sizes = np.array([p.nx for p in probs])
+    picks = []
+    for n in (64, 128, 256, 512):
+        idx = np.nonzero(sizes == n)[0]
+        picks += [int(idx[0]), int(idx[-1])]
+    for i in picks:
+        o = Oracle(probs[i])
+        o.step(steps)
+        err = np.abs(b.save(i).cpu().numpy() - o.f()).max()
+        say(f"    instance {i} n={probs[i].nx} nu={probs[i].nu:.3g} max|df|={err:.3e}")
+        assert err <= TOL
+    b.close()
