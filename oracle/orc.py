@@ -58,6 +58,14 @@ def lib():
         L.orc_feq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
         L.orc_node_moments.argtypes = [C.c_double, _dp, _dp, _dp, _dp]
         L.orc_collision_matrices.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+        L.cnn_param_count.restype = C.c_int32
+        L.cnn_bf16.restype = C.c_double
+        L.cnn_bf16.argtypes = [C.c_double]
+        L.cnn_conv3x3.argtypes = [C.c_int32] * 5 + [_dp, _dp, _dp, _dp]
+        L.cnn_forward.argtypes = [_dp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp]
+        L.cnn_loss_grad.restype = C.c_double
+        L.cnn_loss_grad.argtypes = [_dp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp]
+        L.cnn_apply_correction.argtypes = [C.c_int32, C.c_int32, C.c_double, _dp, _dp, _dp]
         L.orc_collide_step1.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_mixed_derivative.argtypes = [C.c_void_p, _dp, C.c_int32, C.c_int32, _dp]
         L.orc_wall_update.argtypes = [C.c_void_p, _dp]
@@ -194,3 +202,78 @@ def collision_matrices(s: float, sp: float, dt: float):
     lib().orc_collision_matrices(s, sp, dt, _ptr(out))
     m = out.reshape(5, 5, 5)
     return {"Lt": m[0], "ImL": m[1], "Ib": m[2], "Cinv": m[3], "Ainv": m[4]}
+
+
+# ---- closure network (plain FP64 definitions; see cnn_oracle.c) ------------
+
+CNN_CHANNELS = (2, 32, 32, 32, 2)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def cnn_param_count() -> int:
+    return lib().cnn_param_count()
+
+
+def cnn_bf16(v: float) -> float:
+    return lib().cnn_bf16(float(v))
+
+
+def cnn_bf16_array(a: np.ndarray) -> np.ndarray:
+    f = np.vectorize(lib().cnn_bf16, otypes=[np.float64])
+    return f(np.asarray(a, dtype=np.float64))
+
+
+def cnn_conv3x3(a: np.ndarray, w: np.ndarray, bias: Optional[np.ndarray] = None) -> np.ndarray:
+    """a: [B, H, W, cin]; w: [9, cin, cout]; periodic 3x3 convolution -> [B, H, W, cout]."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    B, H, W, cin = a.shape
+    cout = w.shape[2]
+    z = np.empty((B, H, W, cout))
+    b = None if bias is None else np.ascontiguousarray(bias, dtype=np.float64)
+    lib().cnn_conv3x3(B, H, W, cin, cout, _ptr(a), _ptr(w), None if b is None else _ptr(b), _ptr(z))
+    return z
+
+
+def cnn_forward(params: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """x: [B, H, W, 2] -> y: [B, H, W, 2]."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    B, H, W, _ = x.shape
+    y = np.empty((B, H, W, 2))
+    lib().cnn_forward(_ptr(params), B, H, W, _ptr(x), _ptr(y))
+    return y
+
+
+def cnn_loss_grad(params: np.ndarray, x: np.ndarray, target: np.ndarray):
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    t = np.ascontiguousarray(target, dtype=np.float64)
+    B, H, W, _ = x.shape
+    g = np.empty(cnn_param_count())
+    loss = lib().cnn_loss_grad(_ptr(params), B, H, W, _ptr(x), _ptr(t), _ptr(g))
+    return loss, g
+
+
+def cnn_apply_correction(f: np.ndarray, du: np.ndarray, dv: np.ndarray, c: float = 1.0) -> np.ndarray:
+    """f: dense [10, ny, nx] state; returns f + f^eq(u + du, P) - f^eq(u, P)."""
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    ny, nx = f.shape[1:]
+    du = np.ascontiguousarray(du, dtype=np.float64)
+    dv = np.ascontiguousarray(dv, dtype=np.float64)
+    lib().cnn_apply_correction(nx, ny, float(c), _ptr(du), _ptr(dv), _ptr(f))
+    return f
+
+
+def cnn_layer_slices():
+    """(weight slice, bias slice, cin, cout) of each layer in the flat parameter vector."""
+    out, o = [], 0
+    for l in range(4):
+        cin, cout = CNN_CHANNELS[l], CNN_CHANNELS[l + 1]
+        nw = 9 * cin * cout
+        out.append((slice(o, o + nw), slice(o + nw, o + nw + cout), cin, cout))
+        o += nw + cout
+    return out
