@@ -35,7 +35,7 @@ def kernel_sha():
     """Digest of the step's sources (kernels, device header, launch plan); a
     counter summary taken on other sources no longer describes this build."""
     h = hashlib.sha256()
-    for f in ("mdf_fused.hip", "mdf_fused2.hip", "mdf_device.hpp", "mdf_internal.hpp", "mdf_api.hip"):
+    for f in ("mdf_fused.hip", "mdf_fused2.hip", "mdf_device.hpp", "mdf_internal.hpp"):
         h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 

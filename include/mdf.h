@@ -149,6 +149,53 @@ const char* mdf_last_error(const mdf_ctx* ctx);  /* never NULL; "" when none    
 void        mdf_destroy(mdf_ctx* ctx);           /* synchronises; NULL is a no-op  */
 
 /* ---------------------------------------------------------------------------
+ * Learned coarse-grid closure (a project addition, not in the paper): a
+ * four-layer periodic 3x3 convolutional network, channels 2-32-32-32-2, ReLU
+ * after the first three layers, on BF16 matrix cores with FP32 accumulation.
+ * Input x = in_scale*(u, v) per node; output (du, dv) = out_scale*y.
+ * Parameters: one FP32 DEVICE vector of mdf_cnn_param_count() values, layer
+ * by layer W[9][cin][cout] (tap t = 3*(dy+1) + (dx+1)) then b[cout].
+ * Fields: DEVICE FP64 arrays [batch][2][h][w] (u plane then v plane, x
+ * fastest).  The caller owns a DEVICE workspace (256-byte aligned,
+ * mdf_cnn_workspace_size bytes) that keeps the activations of the last
+ * forward call for the backward call.  Asynchronous on `hip_stream`. */
+
+int32_t    mdf_cnn_param_count(void);
+/* 0 unless batch >= 1, h >= 3, w a multiple of 32 and batch*h*w <= 2^26. */
+size_t     mdf_cnn_workspace_size(int32_t batch, int32_t h, int32_t w);
+mdf_status mdf_cnn_forward(void* ws, size_t ws_bytes, const float* params, int32_t batch, int32_t h, int32_t w,
+                           const double* uv, double in_scale, double out_scale, double* duv, void* hip_stream);
+/* Gradient of L = mean((y - target/out_scale)^2) over pixels and both
+ * channels with respect to every parameter, into grad (DEVICE FP32, one
+ * value per parameter), for the activations of the last forward call on ws;
+ * loss (DEVICE double, may be NULL) receives L. */
+mdf_status mdf_cnn_backward(void* ws, size_t ws_bytes, const float* params, int32_t batch, int32_t h, int32_t w,
+                            const double* duv_target, double out_scale, float* grad, double* loss, void* hip_stream);
+/* Copies (DEVICE; any pointer may be NULL) of layer `layer`'s (1..4) BF16
+ * input activation ([P][8] for layer 1, [P][32] otherwise, P = batch*h*w
+ * pixels, channels last) and FP32 pre-activation z ([P][32], [P][2] for
+ * layer 4) from the last forward call, and of the loss gradient at z from
+ * the last backward call, BF16 and FP32 ([P][32] each, channels beyond the
+ * layer's outputs zero).  For checking each layer on its own. */
+mdf_status mdf_cnn_layer_io(const void* ws, size_t ws_bytes, int32_t batch, int32_t h, int32_t w, int32_t layer,
+                            uint16_t* in_bf16, float* z, uint16_t* g_bf16, float* g, void* hip_stream);
+/* Adam step `step` (1, 2, ...) on n FP32 parameters with first/second moment
+ * buffers m, v (DEVICE, zero before step 1). */
+mdf_status mdf_cnn_adam(float* params, const float* grad, float* m, float* v, int32_t n, float lr, float beta1,
+                        float beta2, float eps, int32_t step, void* hip_stream);
+/* Correct the velocity of a periodic, uniform-grid run in place:
+ * f_hat += f^eq(u + du, P) - f^eq(u, P) (eq. 2.2.5), so that the moments
+ * become (u + du, v + dv) with P unchanged.  Guard: the correction is made
+ * only if the corrected field's kinetic energy sum |u|^2/2 does not exceed
+ * ke_ref and its largest central-difference divergence |du/dx + dv/dy| does
+ * not exceed div_tol (both finite); otherwise the state is left alone and
+ * *fell_back = 1.  du, dv: DEVICE [ny][nx], or both NULL to only measure the
+ * current field.  ke_out, div_out, fell_back: host, may be NULL.
+ * Synchronises the context's stream. */
+mdf_status mdf_closure_apply(mdf_ctx* ctx, const double* du, const double* dv, double ke_ref, double div_tol,
+                             double* ke_out, double* div_out, int32_t* fell_back);
+
+/* ---------------------------------------------------------------------------
  * Batches: many independent instances of the same method advanced together
  * (a project addition, not in the paper).  Each instance has its own grid
  * size, viscosity and therefore its own time step dt = CFL dx / c (eq. 3.1)

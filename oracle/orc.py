@@ -209,10 +209,6 @@ def collision_matrices(s: float, sp: float, dt: float):
 CNN_CHANNELS = (2, 32, 32, 32, 2)
 
 
-def _ptr(a):
-    return a.ctypes.data_as(_dp)
-
-
 def cnn_param_count() -> int:
     return lib().cnn_param_count()
 

@@ -52,6 +52,18 @@ SIGNATURES = {
     "mdf_steps": (C.c_int64, [C.c_void_p]),
     "mdf_last_error": (C.c_char_p, [C.c_void_p]),
     "mdf_destroy": (None, [C.c_void_p]),
+    "mdf_cnn_param_count": (C.c_int32, []),
+    "mdf_cnn_workspace_size": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "mdf_cnn_forward": (C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                  C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "mdf_cnn_backward": (C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mdf_cnn_layer_io": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mdf_cnn_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float,
+                               C.c_float, C.c_float, C.c_int32, C.c_void_p]),
+    "mdf_closure_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "mdf_batch_workspace_size": (C.c_size_t, [C.POINTER(mdf_params), C.c_int32]),
     "mdf_batch_init": (C.c_int, [C.POINTER(mdf_params), C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p,
@@ -234,3 +246,44 @@ def mdf_batch_last_error(b) -> str:
 
 def mdf_batch_destroy(b: int):
     lib().mdf_batch_destroy(b)
+
+
+# learned closure -------------------------------------------------------------
+
+def mdf_cnn_param_count() -> int:
+    return lib().mdf_cnn_param_count()
+
+
+def mdf_cnn_workspace_size(batch: int, h: int, w: int) -> int:
+    return lib().mdf_cnn_workspace_size(int(batch), int(h), int(w))
+
+
+def mdf_cnn_forward(ws: int, ws_bytes: int, params: int, batch: int, h: int, w: int, uv: int, in_scale: float,
+                    out_scale: float, duv: int, stream: int):
+    return check(lib().mdf_cnn_forward(ws, ws_bytes, params, int(batch), int(h), int(w), uv, float(in_scale),
+                                       float(out_scale), duv, stream))
+
+
+def mdf_cnn_backward(ws: int, ws_bytes: int, params: int, batch: int, h: int, w: int, target: int,
+                     out_scale: float, grad: int, loss: int, stream: int):
+    return check(lib().mdf_cnn_backward(ws, ws_bytes, params, int(batch), int(h), int(w), target, float(out_scale),
+                                        grad, loss, stream))
+
+
+def mdf_cnn_layer_io(ws: int, ws_bytes: int, batch: int, h: int, w: int, layer: int, in_bf16, z, g_bf16, g,
+                     stream: int):
+    return check(lib().mdf_cnn_layer_io(ws, ws_bytes, int(batch), int(h), int(w), int(layer), in_bf16, z, g_bf16, g,
+                                        stream))
+
+
+def mdf_cnn_adam(params: int, grad: int, m: int, v: int, n: int, lr: float, beta1: float, beta2: float, eps: float,
+                 step: int, stream: int):
+    return check(lib().mdf_cnn_adam(params, grad, m, v, int(n), float(lr), float(beta1), float(beta2), float(eps),
+                                    int(step), stream))
+
+
+def mdf_closure_apply(ctx: int, du: int, dv: int, ke_ref: float, div_tol: float):
+    ke, div, fb = C.c_double(), C.c_double(), C.c_int32()
+    check(lib().mdf_closure_apply(ctx, du, dv, float(ke_ref), float(div_tol), C.byref(ke), C.byref(div),
+                                  C.byref(fb)), ctx)
+    return ke.value, div.value, bool(fb.value)

@@ -650,6 +650,85 @@ void mdf_destroy(mdf_ctx* c)
     delete c;
 }
 
+// ---- learned closure ---------------------------------------------------------
+
+int32_t mdf_cnn_param_count(void) { return mdf::cnn_param_count(); }
+
+size_t mdf_cnn_workspace_size(int32_t batch, int32_t h, int32_t w)
+{
+    if (batch < 1 || h < 3 || w < 32 || (w % 32) != 0 || (int64_t)batch * h * w > (int64_t)1 << 26) return 0;
+    return mdf::cnn_workspace_size(batch, h, w);
+}
+
+static const char* cnn_check(const void* ws, size_t ws_bytes, int32_t batch, int32_t h, int32_t w)
+{
+    const size_t need = mdf_cnn_workspace_size(batch, h, w);
+    if (need == 0) return "batch >= 1, h >= 3, w a multiple of 32 and batch*h*w <= 2^26 required";
+    if (!ws) return "workspace is NULL";
+    if (((uintptr_t)ws & 255) != 0) return "workspace must be 256-byte aligned";
+    if (ws_bytes < need) return "workspace too small";
+    return nullptr;
+}
+
+mdf_status mdf_cnn_forward(void* ws, size_t ws_bytes, const float* params, int32_t batch, int32_t h, int32_t w,
+                           const double* uv, double in_scale, double out_scale, double* duv, void* hip_stream)
+{
+    if (const char* e = cnn_check(ws, ws_bytes, batch, h, w)) return fail(nullptr, MDF_EINVAL, "%s", e);
+    if (!params || !uv || !duv) return fail(nullptr, MDF_EINVAL, "params, uv and duv must be non-NULL");
+    return hip_check(nullptr, mdf::cnn_forward((char*)ws, params, batch, h, w, uv, in_scale, out_scale, duv,
+                                               (hipStream_t)hip_stream), "closure forward");
+}
+
+mdf_status mdf_cnn_backward(void* ws, size_t ws_bytes, const float* params, int32_t batch, int32_t h, int32_t w,
+                            const double* duv_target, double out_scale, float* grad, double* loss, void* hip_stream)
+{
+    if (const char* e = cnn_check(ws, ws_bytes, batch, h, w)) return fail(nullptr, MDF_EINVAL, "%s", e);
+    if (!params || !duv_target || !grad) return fail(nullptr, MDF_EINVAL, "params, target and grad must be non-NULL");
+    return hip_check(nullptr, mdf::cnn_backward((char*)ws, params, batch, h, w, duv_target, out_scale, grad, loss,
+                                                (hipStream_t)hip_stream), "closure backward");
+}
+
+mdf_status mdf_cnn_layer_io(const void* ws, size_t ws_bytes, int32_t batch, int32_t h, int32_t w, int32_t layer,
+                            uint16_t* in_bf16, float* z, uint16_t* g_bf16, float* g, void* hip_stream)
+{
+    if (const char* e = cnn_check(ws, ws_bytes, batch, h, w)) return fail(nullptr, MDF_EINVAL, "%s", e);
+    if (layer < 1 || layer > 4) return fail(nullptr, MDF_EINVAL, "layer must lie in 1..4");
+    return hip_check(nullptr, mdf::cnn_layer_io((const char*)ws, batch, h, w, layer, in_bf16, z, g_bf16, g,
+                                                (hipStream_t)hip_stream), "closure layer copy");
+}
+
+mdf_status mdf_cnn_adam(float* params, const float* grad, float* m, float* v, int32_t n, float lr, float beta1,
+                        float beta2, float eps, int32_t step, void* hip_stream)
+{
+    if (!params || !grad || !m || !v || n < 1 || step < 1) return fail(nullptr, MDF_EINVAL, "bad Adam arguments");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
+        return fail(nullptr, MDF_EINVAL, "Adam needs 0 <= beta < 1 and eps > 0");
+    return hip_check(nullptr, mdf::cnn_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step,
+                                            (hipStream_t)hip_stream), "Adam update");
+}
+
+mdf_status mdf_closure_apply(mdf_ctx* c, const double* du, const double* dv, double ke_ref, double div_tol,
+                             double* ke_out, double* div_out, int32_t* fell_back)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (c->p.bc_x != MDF_BC_PERIODIC || c->p.bc_y != MDF_BC_PERIODIC || c->p.inv_dx_x || c->p.inv_dx_y)
+        return fail(c, MDF_EINVAL, "the closure applies to periodic uniform grids");
+    if ((du == nullptr) != (dv == nullptr)) return fail(c, MDF_EINVAL, "du and dv must both be given or both NULL");
+    const double hx = c->p.lx / c->p.nx, hy = c->p.ly / c->p.ny;
+    double* f = c->f[c->cur];
+    hipError_t e = mdf::launch_closure_guard(c->K, f, du, dv, hx, hy, c->diag_part, c->diag_out, c->stream);
+    double r[2] = {0.0, 0.0};
+    if (e == hipSuccess) e = hipMemcpyAsync(r, c->diag_out, sizeof r, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "closure guard");
+    if (ke_out) *ke_out = r[0];
+    if (div_out) *div_out = r[1];
+    const bool ok = std::isfinite(r[0]) && std::isfinite(r[1]) && r[0] <= ke_ref && r[1] <= div_tol;
+    if (fell_back) *fell_back = (du && !ok) ? 1 : 0;
+    if (!du || !ok) return MDF_OK;
+    return hip_check(c, mdf::launch_closure_apply(c->K, f, du, dv, c->stream), "closure apply");
+}
+
 // ---- batches ---------------------------------------------------------------
 
 size_t mdf_batch_workspace_size(const mdf_params* ps, int32_t count)

@@ -69,4 +69,20 @@ hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, d
 // Same step with one wave per velocity component (64-column strips; tile_w unused).
 hipError_t launch_fused2(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s);
 
+// Learned closure network (BF16 MFMA) and the correction step.
+int32_t cnn_param_count();
+size_t cnn_workspace_size(int B, int H, int W);
+hipError_t cnn_forward(char* ws, const float* params, int B, int H, int W, const double* uv, double in_scale,
+                       double out_scale, double* duv, hipStream_t s);
+hipError_t cnn_backward(char* ws, const float* params, int B, int H, int W, const double* duv_t, double out_scale,
+                        float* grad, double* loss_dev, hipStream_t s);
+hipError_t cnn_layer_io(const char* ws, int B, int H, int W, int layer, unsigned short* in_bf16, float* z_f32,
+                        unsigned short* g_bf16, float* g_f32, hipStream_t s);
+hipError_t cnn_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                    int step, hipStream_t s);
+int closure_guard_blocks(const StepConsts& K);
+hipError_t launch_closure_guard(const StepConsts& K, const double* f, const double* du, const double* dv, double hx,
+                                double hy, double* part, double* out2, hipStream_t s);
+hipError_t launch_closure_apply(const StepConsts& K, double* f, const double* du, const double* dv, hipStream_t s);
+
 }  // namespace mdf
