@@ -119,6 +119,11 @@ mdf_status mdf_diagnostics(mdf_ctx* ctx, double out[8]);
 mdf_status mdf_save(mdf_ctx* ctx, double* f);
 mdf_status mdf_load(mdf_ctx* ctx, const double* f);
 
+/* Restart from the fields u0, v0, p0 (DEVICE, ny*nx doubles each, x fastest):
+ * the state becomes f^eq(u0, v0, p0) at every node, as at mdf_init; the step
+ * counter is kept.  Asynchronous on the context's stream. */
+mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, const double* p0);
+
 /* Kernel selection for the time step: variant 0 = three-pass reference path,
  * 1 = fused single-pass strip kernel with one wave per strip (default for a
  * power-law fluid), 2 = fused single-pass strip kernel with one wave per
@@ -188,11 +193,12 @@ mdf_status mdf_cnn_adam(float* params, const float* grad, float* m, float* v, in
  * become (u + du, v + dv) with P unchanged.  Guard: the correction is made
  * only if the corrected field's kinetic energy sum |u|^2/2 does not exceed
  * ke_ref and its largest central-difference divergence |du/dx + dv/dy| does
- * not exceed div_tol (both finite); otherwise the state is left alone and
- * *fell_back = 1.  du, dv: DEVICE [ny][nx], or both NULL to only measure the
- * current field.  ke_out, div_out, fell_back: host, may be NULL.
- * Synchronises the context's stream. */
-mdf_status mdf_closure_apply(mdf_ctx* ctx, const double* du, const double* dv, double ke_ref, double div_tol,
+ * not exceed div_factor times that of the current field (both finite);
+ * otherwise the state is left alone and *fell_back = 1.  du, dv: DEVICE
+ * [ny][nx], or both NULL to only measure the current field.  *ke_out and
+ * *div_out (host, may be NULL) receive the kinetic energy and divergence of
+ * the field the call leaves.  Synchronises the context's stream. */
+mdf_status mdf_closure_apply(mdf_ctx* ctx, const double* du, const double* dv, double ke_ref, double div_factor,
                              double* ke_out, double* div_out, int32_t* fell_back);
 
 /* ---------------------------------------------------------------------------

@@ -46,6 +46,7 @@ SIGNATURES = {
     "mdf_save": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mdf_load": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mdf_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "mdf_set_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mdf_plan_segments": (C.c_int32, [C.POINTER(mdf_params), C.c_int32, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_int32), C.c_int32]),
     "mdf_dt": (C.c_double, [C.c_void_p]),
@@ -161,6 +162,10 @@ def mdf_plan_segments(p: mdf_params, variant: int, tile_w: int, slots: int, cap:
     buf = (C.c_int32 * (3 * cap))()
     n = lib().mdf_plan_segments(C.byref(p), int(variant), int(tile_w), int(slots), buf, int(cap))
     return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n)]
+
+
+def mdf_set_fields(ctx: int, u0: int, v0: int, p0: int):
+    return check(lib().mdf_set_fields(ctx, u0, v0, p0), ctx)
 
 
 def mdf_dt(ctx: int) -> float:
@@ -282,8 +287,8 @@ def mdf_cnn_adam(params: int, grad: int, m: int, v: int, n: int, lr: float, beta
                                     int(step), stream))
 
 
-def mdf_closure_apply(ctx: int, du: int, dv: int, ke_ref: float, div_tol: float):
+def mdf_closure_apply(ctx: int, du: int, dv: int, ke_ref: float, div_factor: float):
     ke, div, fb = C.c_double(), C.c_double(), C.c_int32()
-    check(lib().mdf_closure_apply(ctx, du, dv, float(ke_ref), float(div_tol), C.byref(ke), C.byref(div),
+    check(lib().mdf_closure_apply(ctx, du, dv, float(ke_ref), float(div_factor), C.byref(ke), C.byref(div),
                                   C.byref(fb)), ctx)
     return ke.value, div.value, bool(fb.value)

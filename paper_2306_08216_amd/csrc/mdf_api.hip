@@ -521,6 +521,15 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     return MDF_OK;
 }
 
+mdf_status mdf_set_fields(mdf_ctx* c, const double* u0, const double* v0, const double* p0)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!u0 || !v0 || !p0) return fail(c, MDF_EINVAL, "u0, v0 and p0 must be non-NULL");
+    hipError_t e = mdf::launch_init(c->K, u0, v0, p0, c->f[c->cur], c->stream);
+    if (e == hipSuccess) e = mdf::launch_wall_fix(c->K, c->f[c->cur], c->stream);
+    return hip_check(c, e, "set fields");
+}
+
 mdf_status mdf_step(mdf_ctx* c, int64_t n)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
@@ -707,7 +716,7 @@ mdf_status mdf_cnn_adam(float* params, const float* grad, float* m, float* v, in
                                             (hipStream_t)hip_stream), "Adam update");
 }
 
-mdf_status mdf_closure_apply(mdf_ctx* c, const double* du, const double* dv, double ke_ref, double div_tol,
+mdf_status mdf_closure_apply(mdf_ctx* c, const double* du, const double* dv, double ke_ref, double div_factor,
                              double* ke_out, double* div_out, int32_t* fell_back)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
@@ -716,16 +725,17 @@ mdf_status mdf_closure_apply(mdf_ctx* c, const double* du, const double* dv, dou
     if ((du == nullptr) != (dv == nullptr)) return fail(c, MDF_EINVAL, "du and dv must both be given or both NULL");
     const double hx = c->p.lx / c->p.nx, hy = c->p.ly / c->p.ny;
     double* f = c->f[c->cur];
+    // r = {KE, max|div| of the current field, KE, max|div| of the corrected one}
     hipError_t e = mdf::launch_closure_guard(c->K, f, du, dv, hx, hy, c->diag_part, c->diag_out, c->stream);
-    double r[2] = {0.0, 0.0};
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
     if (e == hipSuccess) e = hipMemcpyAsync(r, c->diag_out, sizeof r, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_check(c, e, "closure guard");
-    if (ke_out) *ke_out = r[0];
-    if (div_out) *div_out = r[1];
-    const bool ok = std::isfinite(r[0]) && std::isfinite(r[1]) && r[0] <= ke_ref && r[1] <= div_tol;
+    const bool ok = du && std::isfinite(r[2]) && std::isfinite(r[3]) && r[2] <= ke_ref && r[3] <= div_factor * r[1];
+    if (ke_out) *ke_out = ok ? r[2] : r[0];
+    if (div_out) *div_out = ok ? r[3] : r[1];
     if (fell_back) *fell_back = (du && !ok) ? 1 : 0;
-    if (!du || !ok) return MDF_OK;
+    if (!ok) return MDF_OK;
     return hip_check(c, mdf::launch_closure_apply(c->K, f, du, dv, c->stream), "closure apply");
 }
 

@@ -258,74 +258,79 @@ __device__ __forceinline__ void node_uvp(const StepConsts& K, const double* f, i
     node_moments(phi, K.c, u, v, P);
 }
 
-// per block: sum of |u + du|^2 / 2 and max |div_FD(u + du)| (periodic central differences)
+// per block, for the current field (u, v) and the corrected field (u + du, v + dv):
+// sums of |u|^2 / 2 and maxima of |div_FD u| (periodic central differences)
 constexpr int kGuardBlock = 256;
 __global__ __launch_bounds__(kGuardBlock) void k_closure_guard(StepConsts K, const double* __restrict__ f,
                                                                const double* __restrict__ du,
                                                                const double* __restrict__ dv, double hx, double hy,
                                                                double* __restrict__ part)
 {
-    __shared__ double rk[kGuardBlock], rd[kGuardBlock];
-    double ke = 0.0, dmax = 0.0;
+    __shared__ double r[4][kGuardBlock];
+    double kp = 0.0, dp = 0.0, kc = 0.0, dc = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < K.nx * K.ny; i += gridDim.x * blockDim.x) {
         const int x = i % K.nx, y = i / K.nx;
-        double phi[10], u, v, P;
-        auto vel = [&](int xx, int yy, double& uu, double& vv) {
+        double phi[10], P;
+        // plain and corrected velocity at a (wrapped) node
+        auto vel = [&](int xx, int yy, double* w) {
             xx = (xx + K.nx) % K.nx;
             yy = (yy + K.ny) % K.ny;
-            node_uvp(K, f, xx, yy, phi, uu, vv, P);
+            node_uvp(K, f, xx, yy, phi, w[0], w[1], P);
             const size_t j = (size_t)yy * K.nx + xx;
-            if (du) uu += du[j];
-            if (dv) vv += dv[j];
+            w[2] = w[0] + (du ? du[j] : 0.0);
+            w[3] = w[1] + (dv ? dv[j] : 0.0);
         };
-        vel(x, y, u, v);
-        ke += 0.5 * (u * u + v * v);
-        double ue, uw, vn, vs, tmp;
-        vel(x + 1, y, ue, tmp);
-        vel(x - 1, y, uw, tmp);
-        vel(x, y + 1, tmp, vn);
-        vel(x, y - 1, tmp, vs);
-        dmax = fmax(dmax, fabs((ue - uw) / (2.0 * hx) + (vn - vs) / (2.0 * hy)));
+        double c[4], e[4], wv[4], n[4], sv[4];
+        vel(x, y, c);
+        vel(x + 1, y, e);
+        vel(x - 1, y, wv);
+        vel(x, y + 1, n);
+        vel(x, y - 1, sv);
+        kp += 0.5 * (c[0] * c[0] + c[1] * c[1]);
+        kc += 0.5 * (c[2] * c[2] + c[3] * c[3]);
+        dp = fmax(dp, fabs((e[0] - wv[0]) / (2.0 * hx) + (n[1] - sv[1]) / (2.0 * hy)));
+        dc = fmax(dc, fabs((e[2] - wv[2]) / (2.0 * hx) + (n[3] - sv[3]) / (2.0 * hy)));
     }
-    rk[threadIdx.x] = ke;
-    rd[threadIdx.x] = dmax;
+    r[0][threadIdx.x] = kp;
+    r[1][threadIdx.x] = dp;
+    r[2][threadIdx.x] = kc;
+    r[3][threadIdx.x] = dc;
     __syncthreads();
     for (int o = kGuardBlock / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
-            rk[threadIdx.x] += rk[threadIdx.x + o];
-            rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + o]);
+            r[0][threadIdx.x] += r[0][threadIdx.x + o];
+            r[1][threadIdx.x] = fmax(r[1][threadIdx.x], r[1][threadIdx.x + o]);
+            r[2][threadIdx.x] += r[2][threadIdx.x + o];
+            r[3][threadIdx.x] = fmax(r[3][threadIdx.x], r[3][threadIdx.x + o]);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = rk[0];
-        part[2 * blockIdx.x + 1] = rd[0];
-    }
+    if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = r[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(kGuardBlock) void k_closure_guard_final(const double* __restrict__ part, int n,
-                                                                     double* __restrict__ out2)
+                                                                     double* __restrict__ out4)
 {
-    __shared__ double rk[kGuardBlock], rd[kGuardBlock];
-    double k = 0.0, d = 0.0;
+    __shared__ double r[4][kGuardBlock];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < n; i += kGuardBlock) {
-        k += part[2 * i];
-        d = fmax(d, part[2 * i + 1]);
+        a[0] += part[4 * i];
+        a[1] = fmax(a[1], part[4 * i + 1]);
+        a[2] += part[4 * i + 2];
+        a[3] = fmax(a[3], part[4 * i + 3]);
     }
-    rk[threadIdx.x] = k;
-    rd[threadIdx.x] = d;
+    for (int q = 0; q < 4; ++q) r[q][threadIdx.x] = a[q];
     __syncthreads();
     for (int o = kGuardBlock / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
-            rk[threadIdx.x] += rk[threadIdx.x + o];
-            rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + o]);
+            r[0][threadIdx.x] += r[0][threadIdx.x + o];
+            r[1][threadIdx.x] = fmax(r[1][threadIdx.x], r[1][threadIdx.x + o]);
+            r[2][threadIdx.x] += r[2][threadIdx.x + o];
+            r[3][threadIdx.x] = fmax(r[3][threadIdx.x], r[3][threadIdx.x + o]);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out2[0] = rk[0];
-        out2[1] = rd[0];
-    }
+    if (threadIdx.x < 4) out4[threadIdx.x] = r[threadIdx.x][0];
 }
 
 // f_hat += f^eq(u + du, v + dv, P) - f^eq(u, v, P) at every node
@@ -447,19 +452,19 @@ hipError_t cnn_adam(float* p, const float* g, float* m, float* v, int n, float l
     return hipGetLastError();
 }
 
-// at most 4096 blocks (2 partials each): the caller's partial buffer holds 8192 doubles
+// at most 2048 blocks (4 partials each): the caller's partial buffer holds 8192 doubles
 int closure_guard_blocks(const StepConsts& K)
 {
     const int nb = (K.nx * K.ny + kGuardBlock - 1) / kGuardBlock;
-    return nb < 4096 ? nb : 4096;
+    return nb < 2048 ? nb : 2048;
 }
 
 hipError_t launch_closure_guard(const StepConsts& K, const double* f, const double* du, const double* dv, double hx,
-                                double hy, double* part, double* out2, hipStream_t s)
+                                double hy, double* part, double* out4, hipStream_t s)
 {
     const int nb = closure_guard_blocks(K);
     hipLaunchKernelGGL(k_closure_guard, dim3(nb), dim3(kGuardBlock), 0, s, K, f, du, dv, hx, hy, part);
-    hipLaunchKernelGGL(k_closure_guard_final, dim3(1), dim3(kGuardBlock), 0, s, part, nb, out2);
+    hipLaunchKernelGGL(k_closure_guard_final, dim3(1), dim3(kGuardBlock), 0, s, part, nb, out4);
     return hipGetLastError();
 }
 

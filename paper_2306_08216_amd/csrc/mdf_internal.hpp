@@ -82,7 +82,7 @@ hipError_t cnn_adam(float* p, const float* g, float* m, float* v, int n, float l
                     int step, hipStream_t s);
 int closure_guard_blocks(const StepConsts& K);
 hipError_t launch_closure_guard(const StepConsts& K, const double* f, const double* du, const double* dv, double hx,
-                                double hy, double* part, double* out2, hipStream_t s);
+                                double hy, double* part, double* out4, hipStream_t s);
 hipError_t launch_closure_apply(const StepConsts& K, double* f, const double* du, const double* dv, hipStream_t s);
 
 }  // namespace mdf

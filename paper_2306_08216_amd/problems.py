@@ -194,18 +194,22 @@ def random_vortex_fields(n: int, seed: int, kmin: int = 1, kmax: int = 8, urms: 
                 continue
             modes.append((kx, ky, kk))
     phases = rng.uniform(0.0, 2.0 * math.pi, size=len(modes))
-    x = _axis_nodes(n, length, PERIODIC)
-    X, Y = np.meshgrid(x, x, indexing="xy")
     k0 = 2.0 * math.pi / length
-    u = np.zeros((n, n))
-    v = np.zeros((n, n))
+    # psi = sum amp cos(k0 (kx x + ky y) + ph): u = d psi/dy, v = -d psi/dx, i.e.
+    # u = Im sum (-amp k0 ky e^{i ph}) e^{i k0 (kx x + ky y)}.  At the periodic
+    # nodes x_i = i L / n that sum is an inverse DFT (all |k| < n/2), so it is
+    # evaluated exactly (to rounding) with one inverse FFT per component.
+    if 2 * kmax >= n:
+        raise ValueError("random_vortex_fields needs n > 2*kmax")
+    cu = np.zeros((n, n), dtype=complex)
+    cv = np.zeros((n, n), dtype=complex)
     for (kx, ky, kk), ph in zip(modes, phases):
         amp = kk ** -3.0
-        arg = k0 * (kx * X + ky * Y) + ph
-        # psi = amp cos(arg): u = d psi/dy, v = -d psi/dx
-        s = np.sin(arg)
-        u += -amp * k0 * ky * s
-        v += amp * k0 * kx * s
+        e = np.exp(1j * ph) * n * n
+        cu[ky % n, kx % n] += -amp * k0 * ky * e
+        cv[ky % n, kx % n] += amp * k0 * kx * e
+    u = np.ascontiguousarray(np.imag(np.fft.ifft2(cu)))
+    v = np.ascontiguousarray(np.imag(np.fft.ifft2(cv)))
     scale = urms / math.sqrt(np.mean(u * u + v * v))
     u *= scale
     v *= scale

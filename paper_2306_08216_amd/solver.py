@@ -79,6 +79,13 @@ class Solver:
         L.mdf_set_kernel(self.ctx, variant, tile_w, seg_h, prefetch)
         return self
 
+    def set_fields(self, u: torch.Tensor, v: torch.Tensor, p: torch.Tensor):
+        """Restart from (u, v, p) (device FP64 [ny, nx]): f_hat = f^eq at every node."""
+        for t in (u, v, p):
+            assert t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == (self.ny, self.nx)
+        L.mdf_set_fields(self.ctx, u.data_ptr(), v.data_ptr(), p.data_ptr())
+        return self
+
     def step(self, n: int = 1):
         L.mdf_step(self.ctx, n)
         return self
