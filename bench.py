@@ -81,6 +81,11 @@ def main():
                     help="step kernel: 0 three-pass, 1 fused one wave per strip, 2 fused one wave per "
                          "velocity component (-1: the library's default for the workload)")
     ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the library's autotuner (run before the warm-up, outside the timed region)")
+    ap.add_argument("--prefetch", type=int, default=0, help="rows prefetched by the fused kernel (2 or 3)")
+    ap.add_argument("--cost-scales", default="",
+                    help="x,y scalings of the wall-row costs in the balanced partition (instead of autotuning)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after timing, run this many plain state copies (mdf_save: 80 B read + 80 B written "
                          "per node) as the known-size reference for HBM byte counters")
@@ -110,9 +115,19 @@ def main():
         wl = f"periodic Taylor-Green vortex, {args.n}x{args.n} nodes, u0 0.01, nu 0.01, FP64"
     dev = torch.device("cuda:0")
     s = Solver(prob, device="cuda:0")
-    if args.variant >= 0 or args.tile_w or args.seg_h:
-        s.set_kernel(args.variant if args.variant >= 0 else (1 if prob.pl_n != 1.0 else 2), args.tile_w, args.seg_h)
-    variant = args.variant if args.variant >= 0 else (1 if prob.pl_n != 1.0 else 2)
+    tuned = None
+    if args.variant >= 0 or args.tile_w or args.seg_h or args.prefetch or args.cost_scales:
+        variant = args.variant if args.variant >= 0 else (1 if prob.pl_n != 1.0 else 2)
+        s.set_kernel(variant, args.tile_w, args.seg_h, args.prefetch)
+        if args.cost_scales:
+            cx, cy = (float(t) for t in args.cost_scales.split(","))
+            s.set_partition_costs(cx, cy)
+    elif not args.no_autotune:
+        c = s.autotune(10)
+        variant = int(c[0])
+        tuned = {"variant": variant, "prefetch": int(c[1]), "x_wall_cost_scale": c[2], "y_wall_cost_scale": c[3]}
+    else:
+        variant = 1 if prob.pl_n != 1.0 else 2
     kname = {0: "three-pass (k_bar_plus, k_mid, k_hat_new)", 1: "k_fused (one wave per strip)",
              2: "k_fused2 (one wave per velocity component)"}[variant]
     stream = s.stream
@@ -170,6 +185,7 @@ def main():
         "config": {"workload": wl,
                    "kernel": kname,
                    "partition": "balanced one-round segment table" if not args.seg_h else f"seg_h={args.seg_h}",
+                   "autotuned": tuned,
                    "wall_s": round(wall, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

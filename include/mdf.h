@@ -138,6 +138,21 @@ mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, cons
  * stream).  Results agree to rounding whatever the choice. */
 mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t seg_h, int32_t prefetch);
 
+/* Scalings (0..10) of the measured extra per-row cost of segments next to
+ * an x wall and next to a y wall in the balanced partition (1 = measured
+ * costs, 0 = all rows alike); rebuilds the partition (synchronous). */
+mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_wall_scale);
+
+/* Autotuner for this context: times every fused kernel variant (1, and 2
+ * for a Newtonian fluid), prefetch depth (2, 3) and six scalings of the
+ * wall-row cost factors of the balanced partition over `steps` steps of the
+ * run itself, restores the state and step count after each candidate (the
+ * three-pass scratch of the workspace holds the copy), and keeps the
+ * fastest.  choice (host, may be NULL) receives {variant, prefetch, x-wall
+ * scale, y-wall scale, milliseconds per step}.  Synchronises.  Results do
+ * not depend on the choice (to rounding). */
+mdf_status mdf_autotune(mdf_ctx* ctx, int32_t steps, double* choice);
+
 /* Host-only preview of the balanced partition the fused variant (1 or 2)
  * uses for these parameters with `slots` workgroups per round (the library
  * takes 4 per compute unit): writes (strip, first row, end row) triples to

@@ -47,6 +47,8 @@ SIGNATURES = {
     "mdf_load": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mdf_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "mdf_set_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mdf_autotune": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "mdf_set_partition_costs": (C.c_int, [C.c_void_p, C.c_double, C.c_double]),
     "mdf_plan_segments": (C.c_int32, [C.POINTER(mdf_params), C.c_int32, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_int32), C.c_int32]),
     "mdf_dt": (C.c_double, [C.c_void_p]),
@@ -162,6 +164,16 @@ def mdf_plan_segments(p: mdf_params, variant: int, tile_w: int, slots: int, cap:
     buf = (C.c_int32 * (3 * cap))()
     n = lib().mdf_plan_segments(C.byref(p), int(variant), int(tile_w), int(slots), buf, int(cap))
     return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n)]
+
+
+def mdf_autotune(ctx: int, steps: int):
+    out = (C.c_double * 5)()
+    check(lib().mdf_autotune(ctx, int(steps), out), ctx)
+    return tuple(out)
+
+
+def mdf_set_partition_costs(ctx: int, x_wall_scale: float, y_wall_scale: float):
+    return check(lib().mdf_set_partition_costs(ctx, float(x_wall_scale), float(y_wall_scale)), ctx)
 
 
 def mdf_set_fields(ctx: int, u0: int, v0: int, p0: int):

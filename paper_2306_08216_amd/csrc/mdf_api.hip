@@ -33,6 +33,7 @@ struct mdf_ctx {
     mdf::FusedShape shape{64, -1, 2, nullptr, 0};
     int4* seg = nullptr;          // segment table of the balanced partition (device)
     int slots = 1024;             // workgroups one round of the fused step holds
+    double cx_scale = 1.0, cy_scale = 1.0;   // autotuned scalings of the wall-row cost factors
     StepConsts K;
     std::string err;
 };
@@ -272,6 +273,8 @@ mdf_status prepare_shape(mdf_ctx* c)
     }
     double cx, cy;
     segment_costs(c->variant, cx, cy);
+    cx = 1.0 + (cx - 1.0) * c->cx_scale;
+    cy = 1.0 + (cy - 1.0) * c->cy_scale;
     int4* host = new (std::nothrow) int4[kSegCap];
     if (!host) return fail(c, MDF_EDEVICE, "out of host memory");
     const int slots = c->slots < kSegCap ? c->slots : kSegCap;
@@ -640,6 +643,94 @@ int32_t mdf_plan_segments(const mdf_params* p, int32_t variant, int32_t tile_w, 
     }
     delete[] host;
     return n;
+}
+
+mdf_status mdf_set_partition_costs(mdf_ctx* c, double x_wall_scale, double y_wall_scale)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!(x_wall_scale >= 0.0 && x_wall_scale <= 10.0 && y_wall_scale >= 0.0 && y_wall_scale <= 10.0))
+        return fail(c, MDF_EINVAL, "cost scales must lie in [0, 10]");
+    const double ox = c->cx_scale, oy = c->cy_scale;
+    c->cx_scale = x_wall_scale;
+    c->cy_scale = y_wall_scale;
+    const mdf_status s = prepare_shape(c);
+    if (s != MDF_OK) {
+        c->cx_scale = ox;
+        c->cy_scale = oy;
+        (void)prepare_shape(c);
+    }
+    return s;
+}
+
+mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (steps < 1) return fail(c, MDF_EINVAL, "steps must be >= 1");
+    // state backup in the three-pass scratch buffer (same size as a state buffer)
+    const size_t bytes = 10 * (size_t)c->K.pitch * (size_t)c->K.ny * sizeof(double);
+    const int cur0 = c->cur;
+    const int64_t steps0 = c->steps;
+    const int v0 = c->variant;
+    const mdf::FusedShape sh0 = c->shape;
+    const double cxs0 = c->cx_scale, cys0 = c->cy_scale;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->fbp, c->f[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
+    const bool power = c->p.pl_n != 1.0;
+    const double scales[6][2] = {{1.0, 1.0}, {1.35, 1.0}, {1.7, 1.3}, {2.2, 1.6}, {2.8, 2.0}, {3.5, 2.4}};
+    float best = 1e30f;
+    int bv = v0, bp = sh0.prefetch;
+    double bx = cxs0, by = cys0;
+    mdf_status launch = MDF_OK;
+    for (int var = 1; var <= 2 && e == hipSuccess && launch == MDF_OK; ++var) {
+        if (var == 2 && power) continue;   // the per-component kernel exceeds 256 registers for a power law
+        for (int pf = 2; pf <= 3 && e == hipSuccess && launch == MDF_OK; ++pf)
+            for (int sc = 0; sc < 6 && e == hipSuccess && launch == MDF_OK; ++sc) {
+                c->variant = var;
+                c->shape = mdf::FusedShape{64, -1, pf, nullptr, 0};
+                c->cx_scale = scales[sc][0];
+                c->cy_scale = scales[sc][1];
+                if (prepare_shape(c) != MDF_OK) continue;
+                launch = mdf_step(c, 1);   // first launch of this kernel outside the timing
+                if (launch == MDF_OK) e = hipEventRecord(t0, c->stream);
+                if (launch == MDF_OK && e == hipSuccess) launch = mdf_step(c, steps);
+                if (launch == MDF_OK && e == hipSuccess) e = hipEventRecord(t1, c->stream);
+                if (launch == MDF_OK && e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0.0f;
+                if (launch == MDF_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (launch == MDF_OK && e == hipSuccess && ms < best) {
+                    best = ms;
+                    bv = var;
+                    bp = pf;
+                    bx = scales[sc][0];
+                    by = scales[sc][1];
+                }
+                c->cur = cur0;
+                const hipError_t er = hipMemcpyAsync(c->f[cur0], c->fbp, bytes, hipMemcpyDeviceToDevice, c->stream);
+                if (e == hipSuccess) e = er;
+            }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    c->cur = cur0;
+    c->steps = steps0;
+    c->variant = bv;
+    c->shape = mdf::FusedShape{64, -1, bp, nullptr, 0};
+    c->cx_scale = bx;
+    c->cy_scale = by;
+    const mdf_status s = prepare_shape(c);
+    if (e != hipSuccess) return hip_check(c, e, "autotune");
+    if (launch != MDF_OK) return launch;
+    if (s == MDF_OK && choice) {
+        choice[0] = bv;
+        choice[1] = bp;
+        choice[2] = bx;
+        choice[3] = by;
+        choice[4] = best / steps;
+    }
+    return s;
 }
 
 double mdf_dt(const mdf_ctx* c) { return c ? c->K.dt : 0.0; }

@@ -79,6 +79,15 @@ class Solver:
         L.mdf_set_kernel(self.ctx, variant, tile_w, seg_h, prefetch)
         return self
 
+    def autotune(self, steps: int = 10):
+        """Pick the fastest fused kernel and partition for this run (state restored);
+        returns (variant, prefetch, x-wall scale, y-wall scale, ms per step)."""
+        return L.mdf_autotune(self.ctx, steps)
+
+    def set_partition_costs(self, x_wall_scale: float, y_wall_scale: float):
+        L.mdf_set_partition_costs(self.ctx, x_wall_scale, y_wall_scale)
+        return self
+
     def set_fields(self, u: torch.Tensor, v: torch.Tensor, p: torch.Tensor):
         """Restart from (u, v, p) (device FP64 [ny, nx]): f_hat = f^eq at every node."""
         for t in (u, v, p):

@@ -308,3 +308,22 @@ def test_full_size_powerlaw_2048_sampled(gpu):
     err = np.abs(f - o.f()).max()
     say(f"    max|df|={err:.3e}")
     assert err <= TOL
+
+
+def test_autotune_restores_state_and_keeps_parity(gpu):
+    """The single-run autotuner tries every kernel and partition scaling on the
+    run itself; afterwards the state, step count and results are unchanged."""
+    prob, steps = CASES["cavity128"]()
+    say(f"[gpu parity] autotune on cavity128, then {steps} steps")
+    s = gpu(prob, device="cuda:0")
+    s.step(3)
+    before = s.save().cpu().numpy()
+    choice = s.autotune(4)
+    assert int(choice[0]) in (1, 2) and int(choice[1]) in (2, 3) and choice[4] > 0
+    assert s.steps == 3 and np.array_equal(s.save().cpu().numpy(), before)
+    s.step(steps - 3)
+    o, _, _ = oracle_run("cavity128")
+    err = np.abs(s.save().cpu().numpy() - o.f()).max()
+    say(f"    choice={choice} max|df|={err:.3e}")
+    assert err <= TOL
+    s.close()
