@@ -33,7 +33,7 @@ def log(*a):
 
 def kernel_sha():
     """Digest of the step's sources (kernels, device header, launch plan); a
-    counter summary taken on other sources no longer describes this build."""
+    counter summary taken on other sources no longer describes these kernels."""
     h = hashlib.sha256()
     for f in ("mdf_fused.hip", "mdf_fused2.hip", "mdf_device.hpp", "mdf_internal.hpp"):
         h.update(open(os.path.join(CSRC, f), "rb").read())
@@ -92,7 +92,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the MDF-FDLBM step runs on exactly one GPU here; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

@@ -9,8 +9,7 @@
  * matrices exactly as the equations write them (the paper's "2 x 5 x 5"
  * cycles of Sec. 4.2); nothing is fused or reordered.
  *
- * Readings taken where the paper is silent or garbled (all listed in the
- * design notes of the repository):
+ * Readings taken where the paper is silent or garbled:
  *  - c_s^2 follows from the second-moment condition of eq. 2.3.4 with w_j = 1/5;
  *  - the MRT matrix is M^-1 diag(s',s,s,s',s') M with an orthogonal D2Q5 basis;
  *  - eta multiplies the central part of the mixed scheme (eq. 2.2.12); the
