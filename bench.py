@@ -76,7 +76,8 @@ def main():
                          "(n = 0.5) on a tanh-stretched grid; batch: 256 periodic decaying-vortex instances "
                          "of sizes 64..512 advanced together (one launch per step)")
     ap.add_argument("--tile-w", type=int, default=0)
-    ap.add_argument("--seg-h", type=int, default=0, help="rows per segment (0: the library's balanced plan)")
+    ap.add_argument("--seg-h", type=int, default=0,
+                    help="rows per segment; -r: the balanced plan over r rounds of workgroups (0: library default)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="step kernel: 0 three-pass, 1 fused one wave per strip, 2 fused one wave per "
                          "velocity component (-1: the library's default for the workload)")
@@ -123,12 +124,18 @@ def main():
             cx, cy = (float(t) for t in args.cost_scales.split(","))
             s.set_partition_costs(cx, cy)
     elif not args.no_autotune:
-        c = s.autotune(10)
+        c = s.autotune(40)
         variant = int(c[0])
-        tuned = {"variant": variant, "prefetch": int(c[1]), "x_wall_cost_scale": c[2], "y_wall_cost_scale": c[3]}
+        tuned = {"variant": variant, "tile_w": int(c[5]), "prefetch": int(c[1]), "x_wall_cost_scale": c[2],
+                 "y_wall_cost_scale": c[3]}
     else:
         variant = 1 if prob.pl_n != 1.0 else 2
-    kname = {0: "three-pass (k_bar_plus, k_mid, k_hat_new)", 1: "k_fused (one wave per strip)",
+    rounds = -args.seg_h if args.seg_h < 0 else 1
+    partition = (f"seg_h={args.seg_h}" if args.seg_h > 0 else
+                 f"balanced segment table, {rounds} round{'s' if rounds > 1 else ''} of workgroups")
+    tile_w = int(tuned["tile_w"]) if tuned else (args.tile_w or 64)
+    kname = {0: "three-pass (k_bar_plus, k_mid, k_hat_new)",
+             1: "k_fused (one wave per strip)" if tile_w == 64 else f"k_fused ({tile_w}-lane strips, one wave per 64)",
              2: "k_fused2 (one wave per velocity component)"}[variant]
     stream = s.stream
 
@@ -184,7 +191,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl,
                    "kernel": kname,
-                   "partition": "balanced one-round segment table" if not args.seg_h else f"seg_h={args.seg_h}",
+                   "partition": partition,
                    "autotuned": tuned,
                    "wall_s": round(wall, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -128,14 +128,17 @@ mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, cons
  * 1 = fused single-pass strip kernel with one wave per strip (default for a
  * power-law fluid), 2 = fused single-pass strip kernel with one wave per
  * velocity component (default for a Newtonian fluid).
- * tile_w (columns per strip incl. the 8-column halo; 64 or 128; variant 1
- * only), seg_h and prefetch (rows loaded ahead, 2 or 3) apply to the fused
+ * tile_w (columns per strip incl. the 8-column halo, one wave per 64; 64,
+ * 128 or 256, variant 1 only), seg_h and prefetch (rows loaded ahead, 2 or 3;
+ * 2 with 256 lanes) apply to the fused
  * variants; 0 keeps the current value.  seg_h > 0 cuts every strip into
- * segments of seg_h rows; seg_h < 0 (the default) selects the balanced
- * partition: one round of workgroups on the device, with fewer rows in the
- * segments next to walls, whose rows cost more.  Changing the variant or the
- * shape rebuilds that partition (a short synchronous upload on the context's
- * stream).  Results agree to rounding whatever the choice. */
+ * segments of seg_h rows; seg_h = -r (r = 1..4; -1 is the default) selects
+ * the balanced partition over r rounds of waves on the device (one wave per
+ * SIMD per round; a 128-lane strip takes two), with fewer rows in the
+ * segments next to walls, whose rows cost more; seg_h < -4 is MDF_EINVAL.
+ * Changing the variant or the shape rebuilds that partition (a short
+ * synchronous upload on the context's stream).  Results agree to rounding
+ * whatever the choice. */
 mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t seg_h, int32_t prefetch);
 
 /* Scalings (0..10) of the measured extra per-row cost of segments next to
@@ -143,23 +146,25 @@ mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t
  * costs, 0 = all rows alike); rebuilds the partition (synchronous). */
 mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_wall_scale);
 
-/* Autotuner for this context: times every fused kernel variant (1, and 2
- * for a Newtonian fluid), prefetch depth (2, 3) and six scalings of the
- * wall-row cost factors of the balanced partition over `steps` steps of the
- * run itself, restores the state and step count after each candidate (the
- * three-pass scratch of the workspace holds the copy), and keeps the
- * fastest.  choice (host, may be NULL) receives {variant, prefetch, x-wall
- * scale, y-wall scale, milliseconds per step}.  Synchronises.  Results do
+/* Autotuner for this context: times every fused kernel (variant 1 with
+ * tile_w 64, 128 and 256, and variant 2 for a Newtonian fluid), prefetch
+ * depth (2, 3; 2 with 256 lanes) and six scalings of the wall-row cost factors of the one-round
+ * balanced partition over `steps` steps of the run itself, times the three
+ * fastest again over 4 x `steps` steps, restores the state and step count
+ * after each run (the three-pass scratch of the workspace holds the copy),
+ * and keeps the fastest of the second timing.  choice
+ * (host, may be NULL; 6 doubles) receives {variant, prefetch, x-wall scale,
+ * y-wall scale, milliseconds per step, tile_w}.  Synchronises.  Results do
  * not depend on the choice (to rounding). */
 mdf_status mdf_autotune(mdf_ctx* ctx, int32_t steps, double* choice);
 
 /* Host-only preview of the balanced partition the fused variant (1 or 2)
  * uses for these parameters with `slots` workgroups per round (the library
- * takes 4 per compute unit): writes (strip, first row, end row) triples to
- * out[3*i..3*i+2], strips being the tile_w-8 column slices of the grid
- * (tile_w 64 or 128 for variant 1; variant 2 always uses 64), and returns the
- * number of segments, or 0 for invalid input or when cap is too small.  No
- * device work. */
+ * takes 4 waves per compute unit, so 4 * CUs * 64 / tile_w workgroups):
+ * writes (strip, first row, end row) triples to out[3*i..3*i+2], strips
+ * being the tile_w-8 column slices of the grid (tile_w 64, 128 or 256 for
+ * variant 1; variant 2 always uses 64), and returns the number of segments,
+ * or 0 for invalid input or when cap is too small.  No device work. */
 int32_t mdf_plan_segments(const mdf_params* p, int32_t variant, int32_t tile_w, int32_t slots, int32_t* out,
                           int32_t cap);
 

@@ -167,7 +167,7 @@ def mdf_plan_segments(p: mdf_params, variant: int, tile_w: int, slots: int, cap:
 
 
 def mdf_autotune(ctx: int, steps: int):
-    out = (C.c_double * 5)()
+    out = (C.c_double * 6)()
     check(lib().mdf_autotune(ctx, int(steps), out), ctx)
     return tuple(out)
 

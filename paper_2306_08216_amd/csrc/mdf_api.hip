@@ -2,6 +2,7 @@
 // method, workspace carving and kernel launches.  See include/mdf.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -32,7 +33,8 @@ struct mdf_ctx {
     int variant = 2;
     mdf::FusedShape shape{64, -1, 2, nullptr, 0};
     int4* seg = nullptr;          // segment table of the balanced partition (device)
-    int slots = 1024;             // workgroups one round of the fused step holds
+    int slots = 1024;             // 64-lane waves one round of the fused step holds (one per SIMD)
+    int rounds = 1;               // rounds of workgroups the balanced table fills
     double cx_scale = 1.0, cy_scale = 1.0;   // autotuned scalings of the wall-row cost factors
     StepConsts K;
     std::string err;
@@ -277,9 +279,11 @@ mdf_status prepare_shape(mdf_ctx* c)
     cy = 1.0 + (cy - 1.0) * c->cy_scale;
     int4* host = new (std::nothrow) int4[kSegCap];
     if (!host) return fail(c, MDF_EDEVICE, "out of host memory");
-    const int slots = c->slots < kSegCap ? c->slots : kSegCap;
-    // the per-component kernel always runs 64-lane strips
+    // the per-component kernel always runs 64-lane strips; a 128-lane strip
+    // takes two waves, so a round holds half as many of its workgroups
     const int tw = c->variant == 2 ? 64 : sh.tile_w;
+    const int want = c->slots * c->rounds / (tw / 64);
+    const int slots = want < kSegCap ? want : kSegCap;
     const int n = mdf::balanced_partition(c->p.nx, c->p.ny, c->p.bc_x == MDF_BC_WALL, c->p.bc_y == MDF_BC_WALL, tw,
                                           slots, cx, cy, host, kSegCap);
     hipError_t e = hipSuccess;
@@ -604,20 +608,28 @@ mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t s
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
     if (variant < 0 || variant > 2) return fail(c, MDF_EINVAL, "variant must be 0, 1 or 2");
+    if (seg_h < -4) return fail(c, MDF_EINVAL, "seg_h below 0 selects 1 to 4 rounds of the balanced table");
     mdf::FusedShape sh = c->shape;
+    int rounds = c->rounds;
     if (tile_w) sh.tile_w = tile_w;
-    if (seg_h) sh.seg_h = seg_h < 0 ? -1 : seg_h;
+    if (seg_h > 0) sh.seg_h = seg_h;
+    if (seg_h < 0) {
+        sh.seg_h = -1;
+        rounds = -seg_h;
+    }
     if (prefetch) sh.prefetch = prefetch;
     if (!mdf::fused_shape_ok(c->K, sh))
-        return fail(c, MDF_EINVAL, "tile_w must be 64 or 128 and prefetch 2 or 3");
-    const int old_variant = c->variant;
+        return fail(c, MDF_EINVAL, "tile_w must be 64 or 128 with prefetch 2 or 3, or 256 with prefetch 2");
+    const int old_variant = c->variant, old_rounds = c->rounds;
     const mdf::FusedShape old_shape = c->shape;
     c->variant = variant;
     c->shape = sh;
+    c->rounds = rounds;
     const mdf_status s = prepare_shape(c);
     if (s != MDF_OK) {
         c->variant = old_variant;
         c->shape = old_shape;
+        c->rounds = old_rounds;
     }
     return s;
 }
@@ -628,7 +640,7 @@ int32_t mdf_plan_segments(const mdf_params* p, int32_t variant, int32_t tile_w, 
     if (validate(p)) return 0;
     if (variant != 1 && variant != 2) return 0;
     if (variant == 2) tile_w = 64;
-    if (tile_w != 64 && tile_w != 128) return 0;
+    if (tile_w != 64 && tile_w != 128 && tile_w != 256) return 0;
     if (slots < 1 || cap < 1 || !out) return 0;
     double cx, cy;
     segment_costs(variant, cx, cy);
@@ -670,65 +682,80 @@ mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
     const size_t bytes = 10 * (size_t)c->K.pitch * (size_t)c->K.ny * sizeof(double);
     const int cur0 = c->cur;
     const int64_t steps0 = c->steps;
-    const int v0 = c->variant;
-    const mdf::FusedShape sh0 = c->shape;
-    const double cxs0 = c->cx_scale, cys0 = c->cy_scale;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e == hipSuccess) e = hipMemcpyAsync(c->fbp, c->f[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     const bool power = c->p.pl_n != 1.0;
+
+    // candidates: kernel (variant, tile_w, deepest prefetch) in (1, 64, 3),
+    // (1, 128, 3), (1, 256, 2), (2, 64, 3) -- the per-component kernel exceeds
+    // 256 registers for a power law -- times prefetch 2.. times six scalings
+    // of the wall-row cost factors
+    struct Cand {
+        int var, tw, pf;
+        double sx, sy;
+        float ms;
+    };
     const double scales[6][2] = {{1.0, 1.0}, {1.35, 1.0}, {1.7, 1.3}, {2.2, 1.6}, {2.8, 2.0}, {3.5, 2.4}};
-    float best = 1e30f;
-    int bv = v0, bp = sh0.prefetch;
-    double bx = cxs0, by = cys0;
-    mdf_status launch = MDF_OK;
-    for (int var = 1; var <= 2 && e == hipSuccess && launch == MDF_OK; ++var) {
-        if (var == 2 && power) continue;   // the per-component kernel exceeds 256 registers for a power law
-        for (int pf = 2; pf <= 3 && e == hipSuccess && launch == MDF_OK; ++pf)
-            for (int sc = 0; sc < 6 && e == hipSuccess && launch == MDF_OK; ++sc) {
-                c->variant = var;
-                c->shape = mdf::FusedShape{64, -1, pf, nullptr, 0};
-                c->cx_scale = scales[sc][0];
-                c->cy_scale = scales[sc][1];
-                if (prepare_shape(c) != MDF_OK) continue;
-                launch = mdf_step(c, 1);   // first launch of this kernel outside the timing
-                if (launch == MDF_OK) e = hipEventRecord(t0, c->stream);
-                if (launch == MDF_OK && e == hipSuccess) launch = mdf_step(c, steps);
-                if (launch == MDF_OK && e == hipSuccess) e = hipEventRecord(t1, c->stream);
-                if (launch == MDF_OK && e == hipSuccess) e = hipEventSynchronize(t1);
-                float ms = 0.0f;
-                if (launch == MDF_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                if (launch == MDF_OK && e == hipSuccess && ms < best) {
-                    best = ms;
-                    bv = var;
-                    bp = pf;
-                    bx = scales[sc][0];
-                    by = scales[sc][1];
-                }
-                c->cur = cur0;
-                const hipError_t er = hipMemcpyAsync(c->f[cur0], c->fbp, bytes, hipMemcpyDeviceToDevice, c->stream);
-                if (e == hipSuccess) e = er;
-            }
+    std::vector<Cand> cands;
+    const int kernels[4][3] = {{1, 64, 3}, {1, 128, 3}, {1, 256, 2}, {2, 64, 3}};
+    for (int kv = 0; kv < 4; ++kv) {
+        const int var = kernels[kv][0], tw = kernels[kv][1];
+        if (var == 2 && power) continue;
+        for (int pf = 2; pf <= kernels[kv][2]; ++pf)
+            for (int sc = 0; sc < 6; ++sc) cands.push_back(Cand{var, tw, pf, scales[sc][0], scales[sc][1], 1e30f});
     }
+    auto apply = [&](const Cand& k) {
+        c->variant = k.var;
+        c->shape = mdf::FusedShape{k.tw, -1, k.pf, nullptr, 0};
+        c->rounds = 1;
+        c->cx_scale = k.sx;
+        c->cy_scale = k.sy;
+        return prepare_shape(c);
+    };
+    mdf_status launch = MDF_OK;
+    // time one candidate over n steps from the saved state, then restore it
+    auto time_cand = [&](Cand& k, int n) {
+        if (e != hipSuccess || launch != MDF_OK || apply(k) != MDF_OK) return;
+        launch = mdf_step(c, 1);   // first launch of this kernel outside the timing
+        if (launch == MDF_OK) e = hipEventRecord(t0, c->stream);
+        if (launch == MDF_OK && e == hipSuccess) launch = mdf_step(c, n);
+        if (launch == MDF_OK && e == hipSuccess) e = hipEventRecord(t1, c->stream);
+        if (launch == MDF_OK && e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.0f;
+        if (launch == MDF_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (launch == MDF_OK && e == hipSuccess) k.ms = ms / n;
+        c->cur = cur0;
+        const hipError_t er = hipMemcpyAsync(c->f[cur0], c->fbp, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = er;
+    };
+    // pass 1: every candidate over `steps`; pass 2: the three fastest again
+    // over 4 x `steps`, which settles choices within the noise of short runs
+    for (Cand& k : cands) time_cand(k, steps);
+    std::vector<Cand> top(cands);
+    std::stable_sort(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+    if (top.size() > 3) top.resize(3);
+    for (Cand& k : top) time_cand(k, 4 * steps);
+    Cand best{c->variant, c->shape.tile_w, c->shape.prefetch, c->cx_scale, c->cy_scale, 1e30f};
+    for (const Cand& k : top)
+        if (k.ms < best.ms) best = k;
+
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     c->cur = cur0;
     c->steps = steps0;
-    c->variant = bv;
-    c->shape = mdf::FusedShape{64, -1, bp, nullptr, 0};
-    c->cx_scale = bx;
-    c->cy_scale = by;
-    const mdf_status s = prepare_shape(c);
+    const mdf_status s = apply(best);
     if (e != hipSuccess) return hip_check(c, e, "autotune");
     if (launch != MDF_OK) return launch;
     if (s == MDF_OK && choice) {
-        choice[0] = bv;
-        choice[1] = bp;
-        choice[2] = bx;
-        choice[3] = by;
-        choice[4] = best / steps;
+        choice[0] = best.var;
+        choice[1] = best.pf;
+        choice[2] = best.sx;
+        choice[3] = best.sy;
+        choice[4] = best.ms;
+        choice[5] = best.tw;
     }
     return s;
 }

@@ -63,7 +63,10 @@ __device__ __forceinline__ int lclamp(int l)
 // X = [4 components][their non-equilibrium parts g = f - f^eq][P][lane]: the
 // wall rule f_w = f^eq_w + 2 g(n1) - g(n2) then needs no equilibrium of the
 // neighbours, only f^eq at the wall (u = v = 0, P = P(n1)): +-kf P for the u
-// set and 0 for the v set along x.
+// set and 0 for the v set along x.  The inward neighbours n1, n2 are fixed
+// columns (1, 2 at the left wall; nx-2, nx-3 at the right), so every lane
+// reads them at the same LDS address, in the same round trip as its own
+// neighbours, and the lanes next to the wall select the result.
 template <int TW, bool WX>
 __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW], int lane, int x, double nb[4][5],
                                              bool wall_strip)
@@ -73,34 +76,29 @@ __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW
 #pragma unroll
         for (int d = -2; d <= 2; ++d) nb[c][d + 2] = X[c][lclamp<TW>(lane + d)];
     if (WX && wall_strip) {
-        if (x >= 1 && x <= 2) {
-            const int l1 = lclamp<TW>(lane + (1 - x)), l2 = lclamp<TW>(lane + (2 - x));
+        const int x0 = __builtin_amdgcn_readfirstlane(x - lane);   // column of lane 0
+        if (x0 <= 2) {   // the strip holds column 1 or 2
+            const int l1 = lclamp<TW>(1 - x0), l2 = lclamp<TW>(2 - x0);
             const double kp = K.kf * X[8][l1];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const double ew = c >= 2 ? 0.0 : ((c & 1) ? -kp : kp);
                 const double w0 = ew + 2.0 * X[4 + c][l1] - X[4 + c][l2];
-                if (x == 1) {
-                    nb[c][1] = w0;
-                    nb[c][0] = ghost(w0, X[c][l1], X[c][l2]);
-                } else {
-                    nb[c][0] = w0;
-                }
+                const double gh = ghost(w0, X[c][l1], X[c][l2]);
+                nb[c][1] = x == 1 ? w0 : nb[c][1];
+                nb[c][0] = x == 1 ? gh : (x == 2 ? w0 : nb[c][0]);
             }
         }
-        if (x >= K.nx - 3 && x <= K.nx - 2) {
-            const int l1 = lclamp<TW>(lane + (K.nx - 2 - x)), l2 = lclamp<TW>(lane + (K.nx - 3 - x));
+        if (x0 + TW - 1 >= K.nx - 3) {   // the strip holds column nx-3 or nx-2
+            const int l1 = lclamp<TW>(K.nx - 2 - x0), l2 = lclamp<TW>(K.nx - 3 - x0);
             const double kp = K.kf * X[8][l1];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const double ew = c >= 2 ? 0.0 : ((c & 1) ? -kp : kp);
                 const double w0 = ew + 2.0 * X[4 + c][l1] - X[4 + c][l2];
-                if (x == K.nx - 2) {
-                    nb[c][3] = w0;
-                    nb[c][4] = ghost(w0, X[c][l1], X[c][l2]);
-                } else {
-                    nb[c][4] = w0;
-                }
+                const double gh = ghost(w0, X[c][l1], X[c][l2]);
+                nb[c][3] = x == K.nx - 2 ? w0 : nb[c][3];
+                nb[c][4] = x == K.nx - 2 ? gh : (x == K.nx - 3 ? w0 : nb[c][4]);
             }
         }
     }
@@ -448,11 +446,23 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
         // more than 4 nodes away from every wall meets no wall rule, ghost node
         // or wrap: the wall-free march computes exactly the same values with
         // less code and fewer live registers.
+        // Likewise a segment near walls of one axis only runs the march that
+        // handles that axis alone.
         const bool near_x = WX && (xs0 <= 8 || xs1 >= K.nx - 8);
         const bool near_y = WY && (ys0 <= 8 || ys1 >= K.ny - 8);
         if (!near_x && !near_y) {
             fused_march<TW, false, false, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
             return;
+        }
+        if constexpr (WX && WY) {
+            if (!near_y) {
+                fused_march<TW, true, false, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
+                return;
+            }
+            if (!near_x) {
+                fused_march<TW, false, true, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
+                return;
+            }
         }
     }
     fused_march<TW, WX, WY, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
@@ -505,7 +515,7 @@ hipError_t launch_pl(const StepConsts& K, const FusedGrid& G, const double* fin,
 template <int TW>
 hipError_t launch_pf(const StepConsts& K, int pf, const FusedGrid& G, const double* fin, double* fout, hipStream_t s)
 {
-    if (pf <= 2) return launch_pl<TW, 2>(K, G, fin, fout, s);
+    if (pf <= 2 || TW > 128) return launch_pl<TW, 2>(K, G, fin, fout, s);   // 256 lanes: prefetch 2 only
     return launch_pl<TW, 3>(K, G, fin, fout, s);
 }
 
@@ -514,7 +524,8 @@ hipError_t launch_pf(const StepConsts& K, int pf, const FusedGrid& G, const doub
 bool fused_shape_ok(const StepConsts& K, FusedShape sh)
 {
     (void)K;
-    return (sh.tile_w == 64 || sh.tile_w == 128) && sh.prefetch >= 2 && sh.prefetch <= 3;
+    return ((sh.tile_w == 64 || sh.tile_w == 128) && sh.prefetch >= 2 && sh.prefetch <= 3) ||
+           (sh.tile_w == 256 && sh.prefetch == 2);
 }
 
 hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
@@ -556,6 +567,7 @@ hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, d
     switch (sh.tile_w) {
     case 64: return launch_pf<64>(K, sh.prefetch, G, fin, fout, s);
     case 128: return launch_pf<128>(K, sh.prefetch, G, fin, fout, s);
+    case 256: return launch_pf<256>(K, sh.prefetch, G, fin, fout, s);
     default: return hipErrorInvalidValue;
     }
 }

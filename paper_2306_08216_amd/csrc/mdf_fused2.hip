@@ -65,7 +65,8 @@ __device__ __forceinline__ int lc(int l) { return l < 0 ? 0 : (l >= TW2 ? TW2 - 
 // set a from X = [j1, j3, g1, g3, P][lane] with g = f - f^eq; at x walls the
 // wall column takes the wall rule f_w = f^eq_w + 2 g(n1) - g(n2), where f^eq at
 // the wall (u = v = 0, P = P(n1)) is +-kf P for the u set and 0 for the v
-// set, and the column beyond it the ghost node.
+// set, and the column beyond it the ghost node.  n1 and n2 are fixed columns,
+// read by every lane at one LDS address; the lanes next to the wall select.
 template <bool WX>
 __device__ __forceinline__ void x_nb(const StepConsts& K, const double (*X)[TW2], int a, int lane, int x,
                                      double nb[2][5], bool wall_strip)
@@ -75,32 +76,27 @@ __device__ __forceinline__ void x_nb(const StepConsts& K, const double (*X)[TW2]
 #pragma unroll
         for (int d = -2; d <= 2; ++d) nb[c][d + 2] = X[c][lc(lane + d)];
     if (WX && wall_strip) {
-        if (x >= 1 && x <= 2) {
-            const int l1 = lc(lane + (1 - x)), l2 = lc(lane + (2 - x));
+        const int x0 = __builtin_amdgcn_readfirstlane(x - lane);   // column of lane 0
+        if (x0 <= 2) {   // the strip holds column 1 or 2
+            const int l1 = lc(1 - x0), l2 = lc(2 - x0);
             const double kp = a == 0 ? K.kf * X[4][l1] : 0.0;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const double w0 = (c == 0 ? kp : -kp) + 2.0 * X[2 + c][l1] - X[2 + c][l2];
-                if (x == 1) {
-                    nb[c][1] = w0;
-                    nb[c][0] = ghost(w0, X[c][l1], X[c][l2]);
-                } else {
-                    nb[c][0] = w0;
-                }
+                const double gh = ghost(w0, X[c][l1], X[c][l2]);
+                nb[c][1] = x == 1 ? w0 : nb[c][1];
+                nb[c][0] = x == 1 ? gh : (x == 2 ? w0 : nb[c][0]);
             }
         }
-        if (x >= K.nx - 3 && x <= K.nx - 2) {
-            const int l1 = lc(lane + (K.nx - 2 - x)), l2 = lc(lane + (K.nx - 3 - x));
+        if (x0 + TW2 - 1 >= K.nx - 3) {   // the strip holds column nx-3 or nx-2
+            const int l1 = lc(K.nx - 2 - x0), l2 = lc(K.nx - 3 - x0);
             const double kp = a == 0 ? K.kf * X[4][l1] : 0.0;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const double w0 = (c == 0 ? kp : -kp) + 2.0 * X[2 + c][l1] - X[2 + c][l2];
-                if (x == K.nx - 2) {
-                    nb[c][3] = w0;
-                    nb[c][4] = ghost(w0, X[c][l1], X[c][l2]);
-                } else {
-                    nb[c][4] = w0;
-                }
+                const double gh = ghost(w0, X[c][l1], X[c][l2]);
+                nb[c][3] = x == K.nx - 2 ? w0 : nb[c][3];
+                nb[c][4] = x == K.nx - 2 ? gh : (x == K.nx - 3 ? w0 : nb[c][4]);
             }
         }
     }
@@ -450,6 +446,17 @@ __global__ __launch_bounds__(2 * TW2) void k_fused2(StepConsts K, const double* 
         if (!near_x && !near_y) {
             fused2_march<false, false, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, mom, xch);
             return;
+        }
+        // near walls of one axis only: the march that handles that axis alone
+        if constexpr (WX && WY) {
+            if (!near_y) {
+                fused2_march<true, false, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, mom, xch);
+                return;
+            }
+            if (!near_x) {
+                fused2_march<false, true, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, mom, xch);
+                return;
+            }
         }
     }
     fused2_march<WX, WY, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, mom, xch);

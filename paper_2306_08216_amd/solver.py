@@ -81,7 +81,7 @@ class Solver:
 
     def autotune(self, steps: int = 10):
         """Pick the fastest fused kernel and partition for this run (state restored);
-        returns (variant, prefetch, x-wall scale, y-wall scale, ms per step)."""
+        returns (variant, prefetch, x-wall scale, y-wall scale, ms per step, rounds)."""
         return L.mdf_autotune(self.ctx, steps)
 
     def set_partition_costs(self, x_wall_scale: float, y_wall_scale: float):

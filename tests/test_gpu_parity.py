@@ -120,6 +120,7 @@ CASES = {
     "ragged": lambda: (_ragged(), 200),
     "cavity128": lambda: (P.cavity(128, re=1000.0), 1000),
     "cavity_field48": lambda: (_wall_problem(48), 300),
+    "cavity_field520": lambda: (_wall_problem(520), 30),
     "poiseuille32": lambda: (P.poiseuille(32, nu=0.01, force=1e-4), 500),
     "wallx40": lambda: (_wallx(), 300),
     "mapped64": lambda: (_mapped(), 200),
@@ -154,7 +155,8 @@ def _compare(key, Solver, variant, shape=(0, 0)):
     return o
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 8, 2)), (1, (128, 5, 3)), (2, (0, 0)), (2, (0, 64, 2)), (2, (0, 3, 3))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 8, 2)), (1, (128, 5, 3)), (1, (128, -1, 2)), (1, (256, -1, 2)), (2, (0, 0)), (2, (0, 64, 2)),
+                                           (2, (0, 3, 3))])
 def test_taylor_green_64_1000_steps(gpu, variant, shape):
     """The 64^2 Taylor-Green configuration: 1000 FP64 steps agree with the oracle to 1e-12."""
     _compare("tg64", gpu, variant, shape)
@@ -166,7 +168,8 @@ def test_ragged_periodic(gpu, variant, shape):
     _compare("ragged", gpu, variant, shape)
 
 
-@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 9)), (2, (0, 0)), (2, (0, 9, 3))])
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 9)), (1, (128, 9, 3)), (1, (128, -1, 2)), (1, (256, 9, 2)), (1, (64, -2, 3)), (2, (0, 0)),
+                                           (2, (0, 9, 3)), (2, (0, -2))])
 def test_cavity_128_1000_steps(gpu, variant, shape):
     """Lid-driven cavity (the 1024^2 configuration at 128^2): walls on all sides, lid 0.1."""
     _compare("cavity128", gpu, variant, shape)
@@ -175,6 +178,14 @@ def test_cavity_128_1000_steps(gpu, variant, shape):
 @pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 5)), (2, (0, 5)), (2, (0, 48, 3))])
 def test_cavity_with_interior_field(gpu, variant, shape):
     _compare("cavity_field48", gpu, variant, shape)
+
+
+@pytest.mark.parametrize("variant,shape", [(1, (64, -1, 2)), (1, (128, -1, 3)), (1, (256, -1, 2)), (1, (256, 40, 2)),
+                                           (2, (0, -1))])
+def test_wide_cavity_every_tile_width(gpu, variant, shape):
+    """520^2 cavity with an interior field: several strips at every tile width
+    (wall strips and a strip between them), balanced and fixed segments."""
+    _compare("cavity_field520", gpu, variant, shape)
 
 
 @pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 6)), (2, (0, 6)), (2, (0, 32, 3))])
@@ -200,7 +211,7 @@ def test_powerlaw_stretched_cavity(gpu, pl_n, variant, shape):
 
 
 @pytest.mark.parametrize("key", ["stretched144", "plstretched144"])
-@pytest.mark.parametrize("variant,shape", [(1, (64, 10)), (2, (0, 10)), (2, (0, 17, 3))])
+@pytest.mark.parametrize("variant,shape", [(1, (64, 10)), (1, (128, 10, 3)), (1, (256, 10, 2)), (2, (0, 10)), (2, (0, 17, 3))])
 def test_stretched_cavity_interior_segments(gpu, key, variant, shape):
     """Mapped-grid cavities (Newtonian and power law) with segments away from
     every wall next to segments that meet the walls."""
@@ -319,7 +330,7 @@ def test_autotune_restores_state_and_keeps_parity(gpu):
     s.step(3)
     before = s.save().cpu().numpy()
     choice = s.autotune(4)
-    assert int(choice[0]) in (1, 2) and int(choice[1]) in (2, 3) and choice[4] > 0
+    assert int(choice[0]) in (1, 2) and int(choice[1]) in (2, 3) and choice[4] > 0 and int(choice[5]) in (64, 128)
     assert s.steps == 3 and np.array_equal(s.save().cpu().numpy(), before)
     s.step(steps - 3)
     o, _, _ = oracle_run("cavity128")
