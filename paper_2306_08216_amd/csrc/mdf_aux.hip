@@ -123,7 +123,7 @@ __device__ __forceinline__ void derived_node(const StepConsts& K, const double* 
     double u, v, P, fe[10];
     node_moments(fh, K.c, u, v, P);
     equilibrium(u, v, P, K, fe);
-    const double nu = K.pl == PL_NEWTON ? K.nu : powerlaw_nu(K, noneq_shear(fh, fe, K.c), K.theta1);
+    const double nu = K.pl == PL_NEWTON ? K.nu : powerlaw_nu_sq(K, noneq_shear_sq(fh, fe, K.c), K.theta1);
     const double inv = -K.c / (nu + K.theta1);
     const double ux = inv * ((fh[1] - fe[1]) - (fh[3] - fe[3]));
     const double uy = inv * ((fh[2] - fe[2]) - (fh[4] - fe[4]));

@@ -200,33 +200,36 @@ __device__ __forceinline__ void relax(const double* phi, const double* fe, Relax
     }
 }
 
-// sqrt(2 S^:S^) with S^ = -sym(M^ne), M^ne_{ab} = sum_j c_{j,b} (phi - f^eq)_{j,a}.
-__device__ __forceinline__ double noneq_shear(const double* phi, const double* fe, double c)
+// 2 S^:S^ (the square of the non-equilibrium strain magnitude) with
+// S^ = -sym(M^ne), M^ne_{ab} = sum_j c_{j,b} (phi - f^eq)_{j,a}.
+__device__ __forceinline__ double noneq_shear_sq(const double* phi, const double* fe, double c)
 {
     const double mxx = c * ((phi[1] - fe[1]) - (phi[3] - fe[3]));
     const double mxy = c * ((phi[2] - fe[2]) - (phi[4] - fe[4]));
     const double myx = c * ((phi[6] - fe[6]) - (phi[8] - fe[8]));
     const double myy = c * ((phi[7] - fe[7]) - (phi[9] - fe[9]));
     const double s12 = 0.5 * (mxy + myx);
-    return sqrt(2.0 * (mxx * mxx + myy * myy + 2.0 * s12 * s12));
+    return 2.0 * (mxx * mxx + myy * myy + 2.0 * s12 * s12);
 }
 
-// Local power-law viscosity: nu = K (g/(nu + theta))^(n-1), clamped.
-//  n = 1/2: positive root of nu^2 - (K^2/g) nu - K^2 theta/g = 0.
+// Local power-law viscosity nu = K (g/(nu + theta))^(n-1), clamped, from the
+// squared strain magnitude q = g^2:
+//  n = 1/2: positive root of nu^2 - b nu - b theta = 0 with b = K^2/g, i.e.
+//           nu = (b + sqrt(b (b + 4 theta)))/2;
 //  n = 3/2: root of nu^3 + theta nu^2 - K^2 g = 0 by Newton's method from an
 //           upper bound of the root (the cubic is convex and increasing on
 //           nu > 0, so the iterates decrease monotonically to the root).
-__device__ __forceinline__ double powerlaw_nu(const StepConsts& K, double g, double theta)
+__device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, double theta)
 {
     const double Kc = K.nu;
     double nu;
     if (K.pl == PL_HALF) {
-        if (g == 0.0) return K.nu_max;
-        const double b = Kc * Kc / g;
-        nu = 0.5 * (b + sqrt(b * b + 4.0 * Kc * Kc * theta / g));
+        if (q == 0.0) return K.nu_max;
+        const double b = Kc * Kc * rsqrt(q);
+        nu = 0.5 * (b + sqrt(b * (b + 4.0 * theta)));
     } else {
-        if (g == 0.0) return K.nu_min;
-        const double r = Kc * Kc * g;
+        if (q == 0.0) return K.nu_min;
+        const double r = Kc * Kc * sqrt(q);
         // nu^3 <= r and theta nu^2 <= r bound the root from above
         double x = cbrt(r);
         if (theta > 0.0) x = fmin(x, sqrt(r / theta));
@@ -245,7 +248,25 @@ __device__ __forceinline__ double powerlaw_nu(const StepConsts& K, double g, dou
     return fmin(fmax(nu, K.nu_min), K.nu_max);
 }
 
-__device__ __forceinline__ double relax_a(double sig, double dt) { return (1.0 - 0.5 * sig * dt) / (1.0 + 0.5 * sig * dt); }
+// Relaxation factors at a local viscosity nu, with s = c_s^2/nu and
+// s' = s_ratio s.  a(s) = (1 - s dt/2)/(1 + s dt/2) = (nu - t1)/(nu + t1) and
+// q(s) = 1/(1 + s dt/4) = nu/(nu + t3) with t1 = c_s^2 dt/2, t3 = c_s^2 dt/4;
+// the two rates of a pair share one reciprocal.
+__device__ __forceinline__ void relax_ab_nu(const StepConsts& K, double nu, Relax& ra, Relax& rb)
+{
+    const double t = K.theta1, tp = K.s_ratio * K.theta1;
+    const double d = nu + t, dp = nu + tp, inv = 1.0 / (d * dp);
+    const double as = (nu - t) * dp * inv, ap = (nu - tp) * d * inv;
+    ra = Relax{as, ap};
+    rb = Relax{0.25 * (1.0 + 3.0 * as), 0.25 * (1.0 + 3.0 * ap)};
+}
+
+__device__ __forceinline__ Relax relax_q_nu(const StepConsts& K, double nu)
+{
+    const double t = K.theta3, tp = K.s_ratio * K.theta3;
+    const double d = nu + t, dp = nu + tp, inv = nu / (d * dp);
+    return Relax{dp * inv, d * inv};
+}
 
 // Step (1) factors for a node: a(s), a(s') (f_hat^+) and b(s), b(s') (f_bar^+).
 template <int PL>
@@ -257,11 +278,7 @@ __device__ __forceinline__ void step1_factors_t(const StepConsts& K, const doubl
         rb = Relax{K.b_s, K.b_p};
         return;
     }
-    const double nu = powerlaw_nu(K, noneq_shear(fh, fe, K.c), K.theta1);
-    const double s = K.cs2 / nu, sp = K.s_ratio * s;
-    const double as = relax_a(s, K.dt), ap = relax_a(sp, K.dt);
-    ra = Relax{as, ap};
-    rb = Relax{0.25 * (1.0 + 3.0 * as), 0.25 * (1.0 + 3.0 * ap)};
+    relax_ab_nu(K, powerlaw_nu_sq(K, noneq_shear_sq(fh, fe, K.c), K.theta1), ra, rb);
 }
 
 // Step (3) factors q(s), q(s') for the collision of f_bar.
@@ -269,9 +286,7 @@ template <int PL>
 __device__ __forceinline__ Relax step3_factors_t(const StepConsts& K, const double* fb, const double* fe)
 {
     if (PL == PL_NEWTON) return Relax{K.q_s, K.q_p};
-    const double nu = powerlaw_nu(K, noneq_shear(fb, fe, K.c), K.theta3);
-    const double s = K.cs2 / nu, sp = K.s_ratio * s;
-    return Relax{1.0 / (1.0 + 0.25 * s * K.dt), 1.0 / (1.0 + 0.25 * sp * K.dt)};
+    return relax_q_nu(K, powerlaw_nu_sq(K, noneq_shear_sq(fb, fe, K.c), K.theta3));
 }
 
 __device__ __forceinline__ void step1_factors(const StepConsts& K, const double* fh, const double* fe, Relax& ra,

@@ -107,8 +107,8 @@ __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW
 // The march of one strip segment: output columns xs0..xs1-1, rows ys0..ys1-1.
 template <int TW, bool WX, bool WY, bool PLW, int PF, bool UNI>
 __device__ __forceinline__ void fused_march(const StepConsts& K, const double* __restrict__ fin,
-                                            double* __restrict__ fout, int xs0, int xs1, int ys0, int ys1,
-                                            double (*xs)[9][TW])
+                                            double* __restrict__ fout, const double* __restrict__ gyp, int xs0,
+                                            int xs1, int ys0, int ys1, double (*xs)[9][TW])
 {
     const int lane = threadIdx.x;
     const int x = xs0 - 4 + lane;
@@ -129,11 +129,13 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
     const double gxl = UNI ? 0.0 : K.gx[xg];
     const Stencil SXh = UNI ? stencil_of(K.sh[0]) : make_stencil(K, K.lam_h * gxl, true);
     const Stencil SXd = UNI ? stencil_of(K.sd[0]) : make_stencil(K, K.lam_dt * gxl, false);
-    auto y_stencil_h = [&](int row) -> Stencil {
-        return UNI ? stencil_of(K.sh[1]) : make_stencil(K, K.lam_h * K.gy[row], true);
+    // y stencils from the derivative scale gy of the row (mapped grids; the
+    // scale arrives with the row's prefetch)
+    auto y_stencil_h = [&](double gyr) -> Stencil {
+        return UNI ? stencil_of(K.sh[1]) : make_stencil(K, K.lam_h * gyr, true);
     };
-    auto y_stencil_d = [&](int row) -> Stencil {
-        return UNI ? stencil_of(K.sd[1]) : make_stencil(K, K.lam_dt * K.gy[row], false);
+    auto y_stencil_d = [&](double gyr) -> Stencil {
+        return UNI ? stencil_of(K.sd[1]) : make_stencil(K, K.lam_dt * gyr, false);
     };
     // Every row access goes through a buffer descriptor of that one row
     // (scalar registers), so the lane offsets below are the only vector
@@ -160,10 +162,11 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
     // ahead.  Every body issues the same loads and stores whatever its row, so
     // the compiler counts the memory operations in flight exactly and waits
     // only for the row it consumes.
-    double pre[4][10];
-    auto load_row = [&](int k, double* dst) {
+    double pre[4][10], pgy[4] = {0.0, 0.0, 0.0, 0.0};
+    auto load_row = [&](int k, double* dst, double& gyr) {
         const bool on = k <= kend && row_ok(k);   // rows past kend are never used
         const BufRes rs = row_res(fin, row_bytes, on ? wrap_y(k) : 0, on);
+        if (!UNI) gyr = gyp[on ? wrap_y(k) : 0];
         const dvec2 a = buf_load2(rs, vx), b = buf_load2(rs, vx + 16u), c = buf_load2(rs, vx + 32u);
         const dvec2 d = buf_load2(rs, vy), e = buf_load2(rs, vy + 16u);
         dst[0] = a.x; dst[1] = a.y; dst[3] = b.x;   // x part: j = 0, 1, 3 of each set
@@ -173,6 +176,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
     };
 
     double W2[4][2], W4[4][2], F2[4][2], F4[4][2], Qy[4][4], Qx[2][6], Qb[2][6];
+    double gring[4] = {0.0, 0.0, 0.0, 0.0};   // gy of the last four rows (mapped grids)
     double ub_prev[3] = {0, 0, 0}, uf_prev[3] = {0, 0, 0}, pend_b[4] = {0, 0, 0, 0}, pend_f[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -186,7 +190,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
         for (int q = 0; q < 6; ++q) Qx[i][q] = Qb[i][q] = 0.0;
 
 #pragma unroll
-    for (int i = 0; i < PF; ++i) load_row(kbeg + i, pre[i]);
+    for (int i = 0; i < PF; ++i) load_row(kbeg + i, pre[i], pgy[i]);
 
     auto body = [&](auto PC, int k) {
         constexpr int P = decltype(PC)::value;
@@ -194,7 +198,11 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
         double cur[10];
 #pragma unroll
         for (int q = 0; q < 10; ++q) cur[q] = pre[P][q];
-        load_row(k + PF, pre[(P + PF) & 3]);
+        // gy of rows k-1..k-4 by ring slot: m = k-2 in S2, r = k-4 in slot P
+        // (read before the push of row k below)
+        const double gy_m = gring[S2], gy_r = gring[P];
+        gring[P] = pgy[P];
+        load_row(k + PF, pre[(P + PF) & 3], pgy[(P + PF) & 3]);
 
         // ---- A: Step (1) on row k ----
         double fbp[10], fhp[10], ub[3], gb[4];
@@ -274,7 +282,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
         double fm[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, uf[3] = {0.0, 0.0, 0.0};
         double gf[4] = {0.0, 0.0, 0.0, 0.0};
         if (needB) {
-            const Stencil SYh = y_stencil_h(wrap_y(m));
+            const Stencil SYh = y_stencil_h(gy_m);
             double fb[10];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
@@ -361,7 +369,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
         const int r = k - 4;
         const bool outr = (r >= ys0) && (r < ys1) && (WY ? (r >= 1 && r <= K.ny - 2) : true);
         {
-            const Stencil SYd = y_stencil_d(outr ? wrap_y(r) : ys0);
+            const Stencil SYd = y_stencil_d(gy_r);
             double hy[2][2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
@@ -418,7 +426,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
 
 template <int TW, bool WX, bool WY, bool PLW, int PF, bool UNI>
 __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __restrict__ fin, double* __restrict__ fout,
-                                              FusedGrid G)
+                                              const double* __restrict__ gyp, FusedGrid G)
 {
     __shared__ double xs[2][9][TW];
 
@@ -451,21 +459,21 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
         const bool near_x = WX && (xs0 <= 8 || xs1 >= K.nx - 8);
         const bool near_y = WY && (ys0 <= 8 || ys1 >= K.ny - 8);
         if (!near_x && !near_y) {
-            fused_march<TW, false, false, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
+            fused_march<TW, false, false, PLW, PF, UNI>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
             return;
         }
         if constexpr (WX && WY) {
             if (!near_y) {
-                fused_march<TW, true, false, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
+                fused_march<TW, true, false, PLW, PF, UNI>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
                 return;
             }
             if (!near_x) {
-                fused_march<TW, false, true, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
+                fused_march<TW, false, true, PLW, PF, UNI>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
                 return;
             }
         }
     }
-    fused_march<TW, WX, WY, PLW, PF, UNI>(K, fin, fout, xs0, xs1, ys0, ys1, xs);
+    fused_march<TW, WX, WY, PLW, PF, UNI>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
 }
 
 // Batched step: table entry L = (strip, ys0, ys1, instance); every instance
@@ -482,7 +490,7 @@ __global__ __launch_bounds__(64) void k_fused_batch(const BatchInst* __restrict_
     const BatchInst& I = insts[d.w];
     const int xs0 = (int)((unsigned)(d.x * I.K.nx) / (unsigned)I.nstrips);
     const int xs1 = (int)((unsigned)((d.x + 1) * I.K.nx) / (unsigned)I.nstrips);
-    fused_march<64, false, false, PLW, PF, true>(I.K, fin + I.off, fout + I.off, xs0, xs1, d.y, d.z, xs);
+    fused_march<64, false, false, PLW, PF, true>(I.K, fin + I.off, fout + I.off, nullptr, xs0, xs1, d.y, d.z, xs);
 }
 
 template <int TW, bool PLW, int PF, bool UNI>
@@ -490,13 +498,13 @@ hipError_t launch_tw(const StepConsts& K, const FusedGrid& G, const double* fin,
 {
     const dim3 grid(G.chunk * 8), block(TW);
     if (K.bcx && K.bcy)
-        hipLaunchKernelGGL((k_fused<TW, true, true, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, true, true, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, K.gy, G);
     else if (K.bcx)
-        hipLaunchKernelGGL((k_fused<TW, true, false, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, true, false, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, K.gy, G);
     else if (K.bcy)
-        hipLaunchKernelGGL((k_fused<TW, false, true, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, false, true, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, K.gy, G);
     else
-        hipLaunchKernelGGL((k_fused<TW, false, false, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, G);
+        hipLaunchKernelGGL((k_fused<TW, false, false, PLW, PF, UNI>), grid, block, 0, s, K, fin, fout, K.gy, G);
     return hipGetLastError();
 }
 

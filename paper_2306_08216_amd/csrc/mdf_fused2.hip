@@ -104,11 +104,11 @@ __device__ __forceinline__ void x_nb(const StepConsts& K, const double (*X)[TW2]
 
 // Moments of a node for the collision of one set: the two waves swap their
 // partial sums through LDS (M = [quantity][set][lane]); returns (u, v, P) in m,
-// the own set's f^eq in e and, for a power law, the non-equilibrium strain
-// magnitude sqrt(2 S^:S^) of the collided field.
+// the own set's f^eq in e and, for a power law, the squared non-equilibrium
+// strain magnitude 2 S^:S^ of the collided field.
 template <bool PLW>
 __device__ __forceinline__ void collide_moments(const StepConsts& K, double (*M)[2][TW2], int a, int lane,
-                                                const double* phi, double* m, double* e, double& gam_hat)
+                                                const double* phi, double* m, double* e, double& gam_sq)
 {
     const double s = ((phi[0] + phi[1]) + (phi[2] + phi[3])) + phi[4];
     const double q = K.c * (a == 0 ? phi[1] - phi[3] : phi[2] - phi[4]);
@@ -122,7 +122,7 @@ __device__ __forceinline__ void collide_moments(const StepConsts& K, double (*M)
     m[2] = 0.5 * ((a == 0 ? q + qo : qo + q) - (u * u + v * v));
 #pragma unroll
     for (int j = 0; j < 5; ++j) e[j] = feq_j(K, a, j, u, v, m[2]);
-    gam_hat = 0.0;
+    gam_sq = 0.0;
     if (PLW) {
         const double mx = K.c * ((phi[1] - e[1]) - (phi[3] - e[3]));
         const double my = K.c * ((phi[2] - e[2]) - (phi[4] - e[4]));
@@ -133,7 +133,7 @@ __device__ __forceinline__ void collide_moments(const StepConsts& K, double (*M)
         const double mxx = a == 0 ? mx : mxo, mxy = a == 0 ? my : myo;
         const double myx = a == 0 ? mxo : mx, myy = a == 0 ? myo : my;
         const double s12 = 0.5 * (mxy + myx);
-        gam_hat = sqrt(2.0 * (mxx * mxx + myy * myy + 2.0 * s12 * s12));
+        gam_sq = 2.0 * (mxx * mxx + myy * myy + 2.0 * s12 * s12);
     }
 }
 
@@ -245,11 +245,7 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
             collide_moments<PLW>(K, mom[0], a, lane, cur, ub, e, gam);
             Relax ra, rb;
             if (PLW) {
-                const double nu = powerlaw_nu(K, gam, K.theta1);
-                const double s = K.cs2 / nu, sp = K.s_ratio * s;
-                const double as = relax_a(s, K.dt), ap = relax_a(sp, K.dt);
-                ra = Relax{as, ap};
-                rb = Relax{0.25 * (1.0 + 3.0 * as), 0.25 * (1.0 + 3.0 * ap)};
+                relax_ab_nu(K, powerlaw_nu_sq(K, gam, K.theta1), ra, rb);
             } else {
                 ra = Relax{K.a_s, K.a_p};
                 rb = Relax{K.b_s, K.b_p};
@@ -321,9 +317,7 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
             collide_moments<PLW>(K, mom[1], a, lane, fb, uf, e, gam);
             Relax rq;
             if (PLW) {
-                const double nu = powerlaw_nu(K, gam, K.theta3);
-                const double s = K.cs2 / nu, sp = K.s_ratio * s;
-                rq = Relax{1.0 / (1.0 + 0.25 * s * K.dt), 1.0 / (1.0 + 0.25 * sp * K.dt)};
+                rq = relax_q_nu(K, powerlaw_nu_sq(K, gam, K.theta3));
             } else {
                 rq = Relax{K.q_s, K.q_p};
             }
