@@ -218,7 +218,7 @@ def bench_batch(args):
     log("generating 256 instance fields")
     probs = [P.random_vortex(n, sd, nu) for n, nu, sd in inst]
     b = BatchSolver(probs)
-    choice, _ = b.autotune(None, steps=5)
+    choice, _ = b.autotune(None, steps=10)
     nodes = b.nodes
     steps = min(args.steps, 500)
     b.step(min(args.warmup, 50))
@@ -240,7 +240,7 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"batch of 256 periodic decaying vortices, sizes 64..512, {nodes} nodes, FP64",
                    "kernel": {1: "k_fused_batch", 2: "k_fused2_batch"}[choice[0]],
-                   "autotuned": {"variant": choice[0], "prefetch": choice[1], "rounds": choice[2]},
+                   "autotuned": {"variant": choice[0], "tile_w": choice[3], "prefetch": choice[1], "rounds": choice[2]},
                    "workgroups": b.workgroups, "graph": True, "wall_s": round(wall, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

@@ -255,15 +255,19 @@ mdf_status mdf_batch_step(mdf_batch* b, int64_t n);
  * before later work on it.  Results are identical to mdf_batch_step. */
 mdf_status mdf_batch_step_graph(mdf_batch* b, int64_t n);
 
-/* Kernel for the batch: variant 1 (one wave per strip) or 2 (one wave per
- * velocity component), prefetch 2 or 3 rows, and `rounds` (1..8) rounds of
- * workgroups in the balanced partition.  Rebuilds the plan (synchronous). */
-mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t prefetch, int32_t rounds);
+/* Kernel for the batch: variant 1 (one wave per strip; tile_w 64, 128 or 256
+ * lanes per strip, one wave per 64) or 2 (one wave per velocity component;
+ * tile_w 64), tile_w 0 meaning 64; prefetch 2 or 3 rows (2 with 256 lanes);
+ * `rounds` (1..8) rounds of waves in the balanced partition.  Other values
+ * are MDF_EINVAL.  Rebuilds the plan (synchronous). */
+mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t tile_w, int32_t prefetch, int32_t rounds);
 
-/* Autotuner: times each candidate kernel (variant, prefetch, rounds) over
- * `steps` steps on the batch itself, restores the state and step count
- * afterwards, selects the fastest and writes it to choice[0..2] (may be
- * NULL).  Synchronises.  Results do not depend on the choice (to rounding). */
+/* Autotuner: times each candidate kernel (variant, tile_w, prefetch, rounds
+ * 1..3) over `steps` steps on the batch itself, then the three fastest again
+ * over 4 x `steps`, restores the state and step count after each run,
+ * selects the fastest of the second timing and writes {variant, prefetch,
+ * rounds, tile_w} to choice[0..3] (may be NULL).  Synchronises.  Results do
+ * not depend on the choice (to rounding). */
 mdf_status mdf_batch_autotune(mdf_batch* b, int32_t steps, int32_t* choice);
 
 /* Instance i's moments (DEVICE planes of ny_i*nx_i doubles, NULL skips a

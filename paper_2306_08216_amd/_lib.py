@@ -73,7 +73,7 @@ SIGNATURES = {
                                  C.POINTER(C.c_void_p)]),
     "mdf_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "mdf_batch_step_graph": (C.c_int, [C.c_void_p, C.c_int64]),
-    "mdf_batch_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "mdf_batch_set_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "mdf_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "mdf_batch_moments": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mdf_batch_save": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
@@ -226,12 +226,12 @@ def mdf_batch_step_graph(b: int, n: int):
     return bcheck(lib().mdf_batch_step_graph(b, int(n)), b)
 
 
-def mdf_batch_set_kernel(b: int, variant: int, prefetch: int, rounds: int):
-    return bcheck(lib().mdf_batch_set_kernel(b, int(variant), int(prefetch), int(rounds)), b)
+def mdf_batch_set_kernel(b: int, variant: int, tile_w: int, prefetch: int, rounds: int):
+    return bcheck(lib().mdf_batch_set_kernel(b, int(variant), int(tile_w), int(prefetch), int(rounds)), b)
 
 
 def mdf_batch_autotune(b: int, steps: int):
-    choice = (C.c_int32 * 3)()
+    choice = (C.c_int32 * 4)()
     bcheck(lib().mdf_batch_autotune(b, int(steps), choice), b)
     return tuple(choice)
 

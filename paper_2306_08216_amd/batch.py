@@ -73,8 +73,8 @@ class BatchSolver:
         L.mdf_batch_step_graph(self.b, n)
         return self
 
-    def set_kernel(self, variant: int, prefetch: int = 2, rounds: int = 1):
-        L.mdf_batch_set_kernel(self.b, variant, prefetch, rounds)
+    def set_kernel(self, variant: int, prefetch: int = 2, rounds: int = 1, tile_w: int = 64):
+        L.mdf_batch_set_kernel(self.b, variant, tile_w, prefetch, rounds)
         return self
 
     def signature(self) -> str:
@@ -85,15 +85,15 @@ class BatchSolver:
         return f"{self.count}x-{h}"
 
     def autotune(self, cache_path: Optional[str] = None, steps: int = 5):
-        """Pick the fastest (variant, prefetch, rounds); reuse a cached choice for the same signature."""
+        """Pick the fastest (variant, prefetch, rounds, tile_w); reuse a cached choice for the same signature."""
         key = self.signature()
         cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as fh:
                 cache = json.load(fh)
-        if key in cache:
-            v, pf, r = cache[key]["choice"]
-            self.set_kernel(v, pf, r)
+        if key in cache and len(cache[key]["choice"]) == 4:
+            v, pf, r, tw = cache[key]["choice"]
+            self.set_kernel(v, pf, r, tw)
             return tuple(cache[key]["choice"]), True
         choice = L.mdf_batch_autotune(self.b, steps)
         if cache_path:

@@ -321,7 +321,7 @@ struct mdf_batch {
     int table_cap = 0;
     std::vector<mdf::BatchInst> insts;
     bool powerlaw = false;
-    int variant = 2, prefetch = 2, rounds = 1, slots = 1024, nwg = 0;
+    int variant = 2, tile_w = 64, prefetch = 2, rounds = 1, slots = 1024, nwg = 0;
     int cur = 0;
     int64_t steps = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // by starting buffer
@@ -402,14 +402,16 @@ void batch_drop_graphs(mdf_batch* b)
     }
 }
 
-// Balanced partition of all instances' strips over rounds * slots workgroups.
+// Balanced partition of all instances' strips over `rounds` rounds of waves
+// (a strip of tile_w lanes takes tile_w / 64 of them).
 mdf_status batch_plan(mdf_batch* b)
 {
     std::vector<mdf::PlanGrid> g(b->count);
     for (int i = 0; i < b->count; ++i) g[i] = mdf::PlanGrid{b->insts[i].K.nx, b->insts[i].K.ny, false, false};
     std::vector<int4> host(b->table_cap);
-    const int n = mdf::balanced_partition_multi(g.data(), b->count, 64, b->slots * b->rounds, 1.0, 1.0, host.data(),
-                                                b->table_cap);
+    const int tw = b->variant == 2 ? 64 : b->tile_w;
+    const int n = mdf::balanced_partition_multi(g.data(), b->count, tw, b->slots * b->rounds / (tw / 64), 1.0, 1.0,
+                                                host.data(), b->table_cap);
     if (n <= 0) return bfail(b, MDF_EINVAL, "batch too large for its segment table");
     hipError_t e = hipMemcpyAsync(b->d_table, host.data(), sizeof(int4) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -422,7 +424,8 @@ mdf_status batch_plan(mdf_batch* b)
 hipError_t batch_launch(mdf_batch* b, const double* fin, double* fout, hipStream_t s)
 {
     if (b->variant == 1)
-        return mdf::launch_fused_batch(b->d_insts, b->d_table, b->nwg, b->powerlaw, b->prefetch, fin, fout, s);
+        return mdf::launch_fused_batch(b->d_insts, b->d_table, b->nwg, b->powerlaw, b->tile_w, b->prefetch, fin, fout,
+                                       s);
     return mdf::launch_fused2_batch(b->d_insts, b->d_table, b->nwg, b->powerlaw, b->prefetch, fin, fout, s);
 }
 
@@ -989,19 +992,25 @@ mdf_status mdf_batch_step_graph(mdf_batch* b, int64_t n)
     return MDF_OK;
 }
 
-mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t prefetch, int32_t rounds)
+mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t tile_w, int32_t prefetch, int32_t rounds)
 {
     if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
     if (variant != 1 && variant != 2) return bfail(b, MDF_EINVAL, "variant must be 1 or 2");
+    if (tile_w == 0) tile_w = 64;
+    if (tile_w != 64 && (variant == 2 || (tile_w != 128 && tile_w != 256)))
+        return bfail(b, MDF_EINVAL, "tile_w must be 64, 128 or 256 (variant 1) or 64 (variant 2)");
     if (prefetch != 2 && prefetch != 3) return bfail(b, MDF_EINVAL, "prefetch must be 2 or 3");
+    if (tile_w == 256 && prefetch != 2) return bfail(b, MDF_EINVAL, "256-lane strips take prefetch 2");
     if (rounds < 1 || rounds > 8) return bfail(b, MDF_EINVAL, "rounds must lie in 1..8");
-    const int ov = b->variant, op = b->prefetch, orr = b->rounds;
+    const int ov = b->variant, ot = b->tile_w, op = b->prefetch, orr = b->rounds;
     b->variant = variant;
+    b->tile_w = tile_w;
     b->prefetch = prefetch;
     b->rounds = rounds;
     const mdf_status s = batch_plan(b);
     if (s != MDF_OK) {
         b->variant = ov;
+        b->tile_w = ot;
         b->prefetch = op;
         b->rounds = orr;
         (void)batch_plan(b);
@@ -1020,43 +1029,56 @@ mdf_status mdf_batch_autotune(mdf_batch* b, int32_t steps, int32_t* choice)
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e == hipSuccess) e = hipMemcpyAsync(b->backup, b->f[cur0], bytes, hipMemcpyDeviceToDevice, b->stream);
-    float best = 1e30f;
-    int bv = b->variant, bp = b->prefetch, br = b->rounds;
-    const int cand[8][3] = {{2, 2, 1}, {2, 3, 1}, {1, 2, 1}, {1, 3, 1}, {2, 2, 2}, {1, 2, 2}, {2, 2, 3}, {1, 2, 3}};
+    // candidates (variant, tile_w, prefetch, rounds); the per-component kernel
+    // spills for a power law
+    struct Cand {
+        int var, tw, pf, rounds;
+        float ms;
+    };
+    std::vector<Cand> cands;
+    const int kernels[7][3] = {{2, 64, 2}, {2, 64, 3}, {1, 64, 2}, {1, 64, 3}, {1, 128, 2}, {1, 128, 3}, {1, 256, 2}};
+    for (int r = 1; r <= 3; ++r)
+        for (const auto& k : kernels)
+            if (!(k[0] == 2 && b->powerlaw)) cands.push_back(Cand{k[0], k[1], k[2], r, 1e30f});
     mdf_status launch = MDF_OK;
-    for (int c = 0; c < 8 && e == hipSuccess && launch == MDF_OK; ++c) {
-        if (cand[c][0] == 2 && b->powerlaw) continue;   // the per-component kernel spills for a power law
-        if (mdf_batch_set_kernel(b, cand[c][0], cand[c][1], cand[c][2]) != MDF_OK) continue;
+    auto time_cand = [&](Cand& k, int n) {
+        if (e != hipSuccess || launch != MDF_OK) return;
+        if (mdf_batch_set_kernel(b, k.var, k.tw, k.pf, k.rounds) != MDF_OK) return;
         launch = mdf_batch_step(b, 1);   // first launch of this kernel outside the timing
         if (launch == MDF_OK) e = hipEventRecord(t0, b->stream);
-        if (launch == MDF_OK && e == hipSuccess) launch = mdf_batch_step(b, steps);
+        if (launch == MDF_OK && e == hipSuccess) launch = mdf_batch_step(b, n);
         if (launch == MDF_OK && e == hipSuccess) e = hipEventRecord(t1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        if (e == hipSuccess && ms < best) {
-            best = ms;
-            bv = cand[c][0];
-            bp = cand[c][1];
-            br = cand[c][2];
-        }
+        if (launch == MDF_OK && e == hipSuccess) k.ms = ms / n;
         // back to the state the tuning started from
         b->cur = cur0;
         const hipError_t er = hipMemcpyAsync(b->f[cur0], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
         if (e == hipSuccess) e = er;
-    }
+    };
+    // every candidate over `steps`, then the three fastest over 4 x `steps`
+    for (Cand& k : cands) time_cand(k, steps);
+    std::vector<Cand> top(cands);
+    std::stable_sort(top.begin(), top.end(), [](const Cand& a, const Cand& c) { return a.ms < c.ms; });
+    if (top.size() > 3) top.resize(3);
+    for (Cand& k : top) time_cand(k, 4 * steps);
+    Cand best{b->variant, b->tile_w, b->prefetch, b->rounds, 1e30f};
+    for (const Cand& k : top)
+        if (k.ms < best.ms) best = k;
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     b->cur = cur0;
     b->steps = steps0;
+    const mdf_status s = mdf_batch_set_kernel(b, best.var, best.tw, best.pf, best.rounds);
     if (e != hipSuccess) return bhip(b, e, "autotune");
     if (launch != MDF_OK) return launch;
-    const mdf_status s = mdf_batch_set_kernel(b, bv, bp, br);
     if (s == MDF_OK && choice) {
-        choice[0] = bv;
-        choice[1] = bp;
-        choice[2] = br;
+        choice[0] = best.var;
+        choice[1] = best.pf;
+        choice[2] = best.rounds;
+        choice[3] = best.tw;
     }
     return s;
 }

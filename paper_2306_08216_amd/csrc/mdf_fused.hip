@@ -477,20 +477,47 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
 }
 
 // Batched step: table entry L = (strip, ys0, ys1, instance); every instance
-// is periodic on a uniform grid with its own constants and state offset.
-template <bool PLW, int PF>
-__global__ __launch_bounds__(64) void k_fused_batch(const BatchInst* __restrict__ insts, const int4* __restrict__ table,
+// is periodic on a uniform grid with its own constants and state offset, cut
+// into strips of TW - 8 output columns as the plan cuts them.
+template <int TW, bool PLW, int PF>
+__global__ __launch_bounds__(TW) void k_fused_batch(const BatchInst* __restrict__ insts, const int4* __restrict__ table,
                                                     int nwg, int chunk, const double* __restrict__ fin,
                                                     double* __restrict__ fout)
 {
-    __shared__ double xs[2][9][64];
+    __shared__ double xs[2][9][TW];
     const int L = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
     if (L >= nwg) return;
     const int4 d = table[L];
     const BatchInst& I = insts[d.w];
-    const int xs0 = (int)((unsigned)(d.x * I.K.nx) / (unsigned)I.nstrips);
-    const int xs1 = (int)((unsigned)((d.x + 1) * I.K.nx) / (unsigned)I.nstrips);
-    fused_march<64, false, false, PLW, PF, true>(I.K, fin + I.off, fout + I.off, nullptr, xs0, xs1, d.y, d.z, xs);
+    const int nstrips = (I.K.nx + TW - 9) / (TW - 8);
+    const int xs0 = (int)((unsigned)(d.x * I.K.nx) / (unsigned)nstrips);
+    const int xs1 = (int)((unsigned)((d.x + 1) * I.K.nx) / (unsigned)nstrips);
+    fused_march<TW, false, false, PLW, PF, true>(I.K, fin + I.off, fout + I.off, nullptr, xs0, xs1, d.y, d.z, xs);
+}
+
+template <int TW, bool PLW>
+hipError_t launch_batch_tw(const BatchInst* insts, const int4* table, int nwg, int prefetch, const double* fin,
+                           double* fout, hipStream_t s)
+{
+    const int chunk = (nwg + 7) / 8;
+    const dim3 grid(chunk * 8), block(TW);
+    if (prefetch <= 2 || TW > 128)   // 256 lanes: prefetch 2 only
+        hipLaunchKernelGGL((k_fused_batch<TW, PLW, 2>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+    else
+        hipLaunchKernelGGL((k_fused_batch<TW, PLW, 3>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
+    return hipGetLastError();
+}
+
+template <bool PLW>
+hipError_t launch_batch_pl(const BatchInst* insts, const int4* table, int nwg, int tile_w, int prefetch,
+                           const double* fin, double* fout, hipStream_t s)
+{
+    switch (tile_w) {
+    case 64: return launch_batch_tw<64, PLW>(insts, table, nwg, prefetch, fin, fout, s);
+    case 128: return launch_batch_tw<128, PLW>(insts, table, nwg, prefetch, fin, fout, s);
+    case 256: return launch_batch_tw<256, PLW>(insts, table, nwg, prefetch, fin, fout, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int TW, bool PLW, int PF, bool UNI>
@@ -536,24 +563,12 @@ bool fused_shape_ok(const StepConsts& K, FusedShape sh)
            (sh.tile_w == 256 && sh.prefetch == 2);
 }
 
-hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
-                              const double* fin, double* fout, hipStream_t s)
+hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int tile_w,
+                              int prefetch, const double* fin, double* fout, hipStream_t s)
 {
     if (nwg <= 0) return hipErrorInvalidValue;
-    const int chunk = (nwg + 7) / 8;
-    const dim3 grid(chunk * 8), block(64);
-    if (powerlaw) {
-        if (prefetch <= 2)
-            hipLaunchKernelGGL((k_fused_batch<true, 2>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
-        else
-            hipLaunchKernelGGL((k_fused_batch<true, 3>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
-    } else {
-        if (prefetch <= 2)
-            hipLaunchKernelGGL((k_fused_batch<false, 2>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
-        else
-            hipLaunchKernelGGL((k_fused_batch<false, 3>), grid, block, 0, s, insts, table, nwg, chunk, fin, fout);
-    }
-    return hipGetLastError();
+    if (powerlaw) return launch_batch_pl<true>(insts, table, nwg, tile_w, prefetch, fin, fout, s);
+    return launch_batch_pl<false>(insts, table, nwg, tile_w, prefetch, fin, fout, s);
 }
 
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s)

@@ -53,7 +53,7 @@ int balanced_partition_multi(const PlanGrid* grids, int count, int tile_w, int s
 struct BatchInst {
     StepConsts K;
     long long off;   // offset of the instance's state, in doubles, within each state buffer
-    int nstrips;     // 56-column strips of the instance
+    int nstrips;     // 56-column strips of the instance (64-lane strips; wider tiles derive their own)
     int pad;
 };
 
@@ -62,8 +62,8 @@ struct BatchInst {
 // table entries are (strip, ys0, ys1, instance).
 hipError_t launch_fused2_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
                                const double* fin, double* fout, hipStream_t s);
-hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
-                              const double* fin, double* fout, hipStream_t s);
+hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int tile_w,
+                              int prefetch, const double* fin, double* fout, hipStream_t s);
 bool fused_shape_ok(const StepConsts& K, FusedShape sh);
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s);
 // Same step with one wave per velocity component (64-column strips; tile_w unused).

@@ -146,5 +146,5 @@ def test_batch_validation_without_device_work(L):
     s = L.lib().mdf_batch_init(arr, 3, arrp, arrp, arrp, None, 0, None, C.byref(out))
     assert s == L.MDF_EINVAL and out.value is None
     assert L.lib().mdf_batch_step(None, 1) == L.MDF_EINVAL
-    assert L.lib().mdf_batch_set_kernel(None, 1, 2, 1) == L.MDF_EINVAL
+    assert L.lib().mdf_batch_set_kernel(None, 1, 64, 2, 1) == L.MDF_EINVAL
     L.lib().mdf_batch_destroy(None)

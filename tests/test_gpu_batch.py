@@ -68,15 +68,44 @@ def test_batch_matches_each_instance_oracle(gpu):
     b.close()
 
 
-@pytest.mark.parametrize("variant,prefetch,rounds", [(1, 2, 1), (1, 3, 2), (2, 3, 1), (2, 2, 3)])
-def test_batch_kernel_choices_agree(gpu, variant, prefetch, rounds):
+@pytest.mark.parametrize("variant,prefetch,rounds,tile_w", [(1, 2, 1, 64), (1, 3, 2, 64), (2, 3, 1, 64), (2, 2, 3, 64),
+                                                            (1, 3, 1, 128), (1, 2, 2, 256)])
+def test_batch_kernel_choices_agree(gpu, variant, prefetch, rounds, tile_w):
     probs = _mixed()
     steps = 30
-    say(f"[gpu batch] kernel variant={variant} prefetch={prefetch} rounds={rounds}")
-    b = gpu(probs).set_kernel(variant, prefetch, rounds)
+    say(f"[gpu batch] kernel variant={variant} prefetch={prefetch} rounds={rounds} tile_w={tile_w}")
+    b = gpu(probs).set_kernel(variant, prefetch, rounds, tile_w)
     b.step(steps)
     for i in (0, 4, 8):
         err = np.abs(b.save(i).cpu().numpy() - _oracle_f("mixed", i, steps)).max()
+        say(f"    instance {i} max|df|={err:.3e}")
+        assert err <= TOL
+    b.close()
+
+
+def _wide():
+    """Instances wider than one 128- or 256-lane strip, with ragged strip tails."""
+    return [P.random_vortex(n, 600 + i, nu, kmax=6, urms=0.03) for i, (n, nu) in enumerate(((300, 2e-3), (64, 1e-2),
+                                                                                            (260, 5e-3)))]
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_wide(i, steps):
+    from oracle.orc import Oracle
+    o = Oracle(_wide()[i])
+    o.step(steps)
+    return o.f()
+
+
+@pytest.mark.parametrize("tile_w,prefetch", [(128, 3), (256, 2)])
+def test_batch_wide_strips(gpu, tile_w, prefetch):
+    probs = _wide()
+    steps = 20
+    say(f"[gpu batch] wide instances sizes={[p.nx for p in probs]} tile_w={tile_w} prefetch={prefetch}")
+    b = gpu(probs).set_kernel(1, prefetch, 1, tile_w)
+    b.step(steps)
+    for i in range(len(probs)):
+        err = np.abs(b.save(i).cpu().numpy() - _oracle_wide(i, steps)).max()
         say(f"    instance {i} max|df|={err:.3e}")
         assert err <= TOL
     b.close()
@@ -120,6 +149,7 @@ def test_autotune_restores_state_and_caches(gpu, tmp_path):
     cache = str(tmp_path / "tune.json")
     choice, cached = b.autotune(cache, steps=3)
     assert not cached and choice[0] in (1, 2) and choice[1] in (2, 3) and 1 <= choice[2] <= 3
+    assert choice[3] in (64, 128, 256)
     assert b.steps == 4
     for i in range(len(probs)):
         assert np.array_equal(before[i], b.save(i).cpu().numpy())
