@@ -173,10 +173,13 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
 
 // Greedy segmentation of every strip of every grid at cost budget T (row
 // units); returns the number of segments, or -1 if some segment cannot hold a
-// single row.
+// single row.  A segment of h rows marches h + 8 rows rounded up to whole
+// groups of 4 (the kernels' unrolled loop), so its height is chosen with
+// h + 8 a multiple of 4 where the budget allows.
 int segment_strips(const mdf::PlanGrid* grids, int count, int tile_w, double cx, double cy, double T, int4* out,
                    int cap)
 {
+    auto rows_for = [](double budget) { return ((int)std::floor(budget) & ~3) - 8; };
     int n = 0;
     for (int g = 0; g < count; ++g) {
         const int nx = grids[g].nx, ny = grids[g].ny;
@@ -190,8 +193,8 @@ int segment_strips(const mdf::PlanGrid* grids, int count, int tile_w, double cx,
             int y = 0;
             while (y < ny) {
                 double f = fx * ((wall_y && y <= 8) ? cy : 1.0);
-                int h = (int)std::floor(T / f) - 8;
-                if (wall_y && y + h >= ny - 8) h = (int)std::floor(T / (fx * cy)) - 8;   // ends next to the top wall
+                int h = rows_for(T / f);
+                if (wall_y && y + h >= ny - 8) h = rows_for(T / (fx * cy));   // ends next to the top wall
                 if (h < 1) return -1;
                 if (y + h > ny) h = ny - y;
                 if (out && n < cap) out[n] = make_int4(s, y, y + h, g);
@@ -213,7 +216,7 @@ int balanced_partition_multi(const PlanGrid* grids, int count, int tile_w, int s
     int maxny = 0;
     for (int g = 0; g < count; ++g) maxny = grids[g].ny > maxny ? grids[g].ny : maxny;
     const double fmax = cx * cy;
-    double lo = 9.0, hi = fmax * (maxny + 8) + 1.0;   // hi: one segment per strip always fits
+    double lo = 9.0, hi = fmax * (maxny + 12) + 1.0;   // hi: one segment per strip always fits
     if (segment_strips(grids, count, tile_w, cx, cy, hi, nullptr, 0) > slots) {
         lo = hi;   // more strips than slots: one segment each
     } else {
