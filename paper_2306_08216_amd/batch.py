@@ -78,20 +78,22 @@ class BatchSolver:
         return self
 
     def signature(self) -> str:
-        """Key of the autotuner cache: the instance sizes, the fluid model and the device."""
+        """Key of the autotuner cache: the instance sizes, the fluid model and the
+        device (architecture and compute-unit count)."""
         sizes = sorted((p.nx, p.ny) for p in self.probs)
-        name = torch.cuda.get_device_name(self.device)
-        h = hashlib.sha256(json.dumps([sizes, self.probs[0].pl_n, name]).encode()).hexdigest()[:16]
+        props = torch.cuda.get_device_properties(self.device)
+        dev = [str(getattr(props, "gcnArchName", "")).split(":")[0], int(props.multi_processor_count)]
+        h = hashlib.sha256(json.dumps([sizes, self.probs[0].pl_n, dev]).encode()).hexdigest()[:16]
         return f"{self.count}x-{h}"
 
-    def autotune(self, cache_path: Optional[str] = None, steps: int = 5):
+    def autotune(self, cache_path: Optional[str] = None, steps: int = 5, retune: bool = False):
         """Pick the fastest (variant, prefetch, rounds, tile_w); reuse a cached choice for the same signature."""
         key = self.signature()
         cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as fh:
                 cache = json.load(fh)
-        if key in cache and len(cache[key]["choice"]) == 4:
+        if key in cache and len(cache[key]["choice"]) == 4 and not retune:
             v, pf, r, tw = cache[key]["choice"]
             self.set_kernel(v, pf, r, tw)
             return tuple(cache[key]["choice"]), True

@@ -696,21 +696,24 @@ mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
 
     // candidates: kernel (variant, tile_w, deepest prefetch) in (1, 64, 3),
     // (1, 128, 3), (1, 256, 2), (2, 64, 3) -- the per-component kernel exceeds
-    // 256 registers for a power law -- times prefetch 2.. times six scalings
+    // 256 registers for a power law -- times prefetch 2.. times eight scalings
     // of the wall-row cost factors
     struct Cand {
         int var, tw, pf;
         double sx, sy;
         float ms;
     };
-    const double scales[6][2] = {{1.0, 1.0}, {1.35, 1.0}, {1.7, 1.3}, {2.2, 1.6}, {2.8, 2.0}, {3.5, 2.4}};
+    // (below 1 for wide strips, where a wall strip's extra work is spread
+    // over more columns)
+    const double scales[8][2] = {{0.3, 0.6}, {0.6, 0.8}, {1.0, 1.0}, {1.35, 1.0},
+                                 {1.7, 1.3}, {2.2, 1.6}, {2.8, 2.0}, {3.5, 2.4}};
     std::vector<Cand> cands;
     const int kernels[4][3] = {{1, 64, 3}, {1, 128, 3}, {1, 256, 2}, {2, 64, 3}};
     for (int kv = 0; kv < 4; ++kv) {
         const int var = kernels[kv][0], tw = kernels[kv][1];
         if (var == 2 && power) continue;
         for (int pf = 2; pf <= kernels[kv][2]; ++pf)
-            for (int sc = 0; sc < 6; ++sc) cands.push_back(Cand{var, tw, pf, scales[sc][0], scales[sc][1], 1e30f});
+            for (int sc = 0; sc < 8; ++sc) cands.push_back(Cand{var, tw, pf, scales[sc][0], scales[sc][1], 1e30f});
     }
     auto apply = [&](const Cand& k) {
         c->variant = k.var;

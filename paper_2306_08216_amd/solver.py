@@ -6,6 +6,9 @@ all arithmetic runs in the HIP kernels of libmdf.so.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
+import os
 from typing import Optional
 
 import numpy as np
@@ -81,8 +84,47 @@ class Solver:
 
     def autotune(self, steps: int = 10):
         """Pick the fastest fused kernel and partition for this run (state restored);
-        returns (variant, prefetch, x-wall scale, y-wall scale, ms per step, rounds)."""
+        returns (variant, prefetch, x-wall scale, y-wall scale, ms per step, tile_w)."""
         return L.mdf_autotune(self.ctx, steps)
+
+    def signature(self) -> str:
+        """Key of a tuning cache: grid, boundaries, fluid model, mapping and device
+        (architecture and compute-unit count)."""
+        p = self.prob
+        props = torch.cuda.get_device_properties(self.device)
+        dev = [str(getattr(props, "gcnArchName", "")).split(":")[0], int(props.multi_processor_count)]
+        key = [p.nx, p.ny, p.bc_x, p.bc_y, p.pl_n, p.inv_dx_x is None and p.inv_dx_y is None, dev]
+        return f"{p.nx}x{p.ny}-" + hashlib.sha256(json.dumps(key).encode()).hexdigest()[:16]
+
+    def apply_choice(self, choice):
+        """Select (variant, tile_w, prefetch, x-wall scale, y-wall scale) without timing anything."""
+        variant, tile_w, prefetch, sx, sy = choice
+        self.set_kernel(int(variant), int(tile_w), -1, int(prefetch))
+        self.set_partition_costs(float(sx), float(sy))
+        return self
+
+    def tuned(self, cache_path: Optional[str] = None, steps: int = 10, retune: bool = False):
+        """The kernel choice for this run from the tuning cache at `cache_path`
+        (same signature), else from the autotuner, whose choice is then stored
+        there.  Returns ((variant, tile_w, prefetch, x scale, y scale), cached)."""
+        key = self.signature()
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        if key in cache and not retune:
+            choice = tuple(cache[key]["choice"])
+            self.apply_choice(choice)
+            return choice, True
+        c = self.autotune(steps)
+        choice = (int(c[0]), int(c[5]), int(c[1]), float(c[2]), float(c[3]))
+        if cache_path:
+            cache[key] = {"choice": list(choice), "nx": self.nx, "ny": self.ny, "ms_per_step": c[4]}
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return choice, False
 
     def set_partition_costs(self, x_wall_scale: float, y_wall_scale: float):
         L.mdf_set_partition_costs(self.ctx, x_wall_scale, y_wall_scale)
