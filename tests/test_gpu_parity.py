@@ -338,3 +338,28 @@ def test_autotune_restores_state_and_keeps_parity(gpu):
     say(f"    choice={choice} max|df|={err:.3e}")
     assert err <= TOL
     s.close()
+
+
+def test_tuning_cache_round_trip(gpu, tmp_path):
+    """Solver.tuned: the first call tunes and stores the choice under the run's
+    signature, the second reuses it; the state is untouched and parity holds."""
+    import json
+    prob, steps = CASES["cavity128"]()
+    say("[gpu parity] tuning cache on cavity128")
+    cache = str(tmp_path / "tuning.json")
+    s = gpu(prob, device="cuda:0")
+    before = s.save().cpu().numpy()
+    choice, cached = s.tuned(cache, steps=3)
+    assert not cached and int(choice[0]) in (1, 2) and int(choice[1]) in (64, 128, 256)
+    assert np.array_equal(s.save().cpu().numpy(), before) and s.steps == 0
+    assert json.load(open(cache))[s.signature()]["choice"] == list(choice)
+    s2 = gpu(prob, device="cuda:0")
+    choice2, cached2 = s2.tuned(cache)
+    assert cached2 and tuple(choice2) == tuple(choice)
+    s2.step(steps)
+    o, _, _ = oracle_run("cavity128")
+    err = np.abs(s2.save().cpu().numpy() - o.f()).max()
+    say(f"    choice={choice} max|df|={err:.3e}")
+    assert err <= TOL
+    s.close()
+    s2.close()
