@@ -63,6 +63,22 @@ def measured_traffic(workload, n, choice):
     return float(m_b.group(1))
 
 
+def measured_batch_traffic(choice):
+    """HBM bytes per batched step from the committed counter summary, if taken
+    on the current sources with the same (variant, prefetch, rounds, tile_w)."""
+    path = os.path.join(PROFILES, "fused_step_batch256_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"kernel_sha:\s*([0-9a-f]+)", txt)
+    m_ch = re.search(r"choice:\s*([^\n]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    want = " ".join(str(int(v)) for v in choice)
+    if not (m_sha and m_ch and m_b) or m_sha.group(1) != kernel_sha() or m_ch.group(1).strip() != want:
+        return None
+    return float(m_b.group(1))
+
+
 def cpu_baseline(prob, steps):
     """The CPU oracle (single thread, as it stands) on `steps` steps of the same workload."""
     from oracle.orc import Oracle
@@ -255,6 +271,13 @@ def bench_batch(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
+    if args.copy_calib > 0:
+        # known-size copies (k_pack, 80 B read + 80 B written per node) of the
+        # largest instances, the reference for the byte counters
+        big = sorted(range(b.count), key=lambda i: -probs[i].nodes)[:args.copy_calib]
+        for i in big:
+            b.save(i)
+        torch.cuda.synchronize()
     mlups = nodes * steps / (ms / 1e3) / 1e6
     achieved = BYTES_PER_NODE * nodes / (ms / 1e3 / steps) / 1e9
     out = {
@@ -267,7 +290,7 @@ def bench_batch(args):
                                  "from_cache": cached},
                    "workgroups": b.workgroups, "graph": True, "wall_s": round(wall, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_batch_traffic(choice),
                      "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes},
         "cpu_baseline": None,
     }
