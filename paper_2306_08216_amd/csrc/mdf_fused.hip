@@ -10,6 +10,8 @@
 //   B'  x-neighbours of f(t+h) through LDS; x part of Step (4) for row m -> store
 //   C   y part of Step (4) for row r = k-4 from the f(t+h) window -> store (eq. 2.3.24)
 // so HBM sees one read and one write of the 10 distribution planes per node.
+// B does not depend on the exchange of A', so both rows publish their
+// x-streamed components first and meet at a single LDS barrier per row.
 // Row windows are 4-deep register rings indexed by (row - first row) & 3; the
 // march is unrolled by 4 so every ring index is a compile-time constant.
 //
@@ -250,29 +252,20 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
             }
         }
 
-        // ---- A': x part of the half step for row k ----
-        double bx[6];
-        {
-            double(*X)[TW] = xs[0];
-            X[0][lane] = fbp[1];
-            X[1][lane] = fbp[3];
-            X[2][lane] = fbp[6];
-            X[3][lane] = fbp[8];
-            if (WX && wall_strip) {
+        // ---- A' (publish): the x-streamed components of row k ----
+        // Both exchanges of the body (A' for row k, B' for row m) go through
+        // one barrier.  Their buffers alternate with the body's parity, so a
+        // wave's next writes never reach a buffer another wave still reads.
+        double(*XA)[TW] = xs[2 * (P & 1)];
+        double(*XB)[TW] = xs[2 * (P & 1) + 1];
+        XA[0][lane] = fbp[1];
+        XA[1][lane] = fbp[3];
+        XA[2][lane] = fbp[6];
+        XA[3][lane] = fbp[8];
+        if (WX && wall_strip) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) X[4 + c][lane] = gb[c];
-                X[8][lane] = ub[2];
-            }
-            exchange_barrier<TW / 64>();
-            double nb[4][5];
-            x_neighbours<TW, WX>(K, X, lane, x, nb, wall_strip);
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                bx[3 * a + 0] = fbp[5 * a] + K.hwf[a];
-                bx[3 * a + 1] = upd_pos(SXh, K.hwf[a], nb[2 * a][0], nb[2 * a][1], nb[2 * a][2], nb[2 * a][3]);
-                bx[3 * a + 2] =
-                    upd_neg(SXh, K.hwf[a], nb[2 * a + 1][1], nb[2 * a + 1][2], nb[2 * a + 1][3], nb[2 * a + 1][4]);
-            }
+            for (int c = 0; c < 4; ++c) XA[4 + c][lane] = gb[c];
+            XA[8][lane] = ub[2];
         }
 
         // ---- B: half step (y part) and Step (3) on row m = k-2 ----
@@ -333,23 +326,38 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
             }
         }
 
+        // ---- B' (publish): the x-streamed components of f(t+h) on row m ----
+        XB[0][lane] = fm[1];
+        XB[1][lane] = fm[3];
+        XB[2][lane] = fm[6];
+        XB[3][lane] = fm[8];
+        if (WX && wall_strip) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) XB[4 + c][lane] = gf[c];
+            XB[8][lane] = uf[2];
+        }
+        exchange_barrier<TW / 64>();
+
+        // ---- A': x part of the half step for row k ----
+        double bx[6];
+        {
+            double nb[4][5];
+            x_neighbours<TW, WX>(K, XA, lane, x, nb, wall_strip);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                bx[3 * a + 0] = fbp[5 * a] + K.hwf[a];
+                bx[3 * a + 1] = upd_pos(SXh, K.hwf[a], nb[2 * a][0], nb[2 * a][1], nb[2 * a][2], nb[2 * a][3]);
+                bx[3 * a + 2] =
+                    upd_neg(SXh, K.hwf[a], nb[2 * a + 1][1], nb[2 * a + 1][2], nb[2 * a + 1][3], nb[2 * a + 1][4]);
+            }
+        }
+
         // ---- B': x part of Step (4) on row m ----
         const bool outm = needB && (m >= ys0) && (m < ys1);
         {
             double h[2][3];
-            double(*X)[TW] = xs[1];
-            X[0][lane] = fm[1];
-            X[1][lane] = fm[3];
-            X[2][lane] = fm[6];
-            X[3][lane] = fm[8];
-            if (WX && wall_strip) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) X[4 + c][lane] = gf[c];
-                X[8][lane] = uf[2];
-            }
-            exchange_barrier<TW / 64>();
             double nb[4][5];
-            x_neighbours<TW, WX>(K, X, lane, x, nb, wall_strip);
+            x_neighbours<TW, WX>(K, XB, lane, x, nb, wall_strip);
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 h[a][0] = Qx[P & 1][3 * a + 0] + K.dwf[a];
@@ -428,7 +436,7 @@ template <int TW, bool WX, bool WY, bool PLW, int PF, bool UNI>
 __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __restrict__ fin, double* __restrict__ fout,
                                               const double* __restrict__ gyp, FusedGrid G)
 {
-    __shared__ double xs[2][9][TW];
+    __shared__ double xs[4][9][TW];
 
     // XCD-aware order: consecutive segments of a strip land on the same XCD
     const int L = (int)(blockIdx.x % 8) * G.chunk + (int)(blockIdx.x / 8);
@@ -484,7 +492,7 @@ __global__ __launch_bounds__(TW) void k_fused_batch(const BatchInst* __restrict_
                                                     int nwg, int chunk, const double* __restrict__ fin,
                                                     double* __restrict__ fout)
 {
-    __shared__ double xs[2][9][TW];
+    __shared__ double xs[4][9][TW];
     const int L = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
     if (L >= nwg) return;
     const int4 d = table[L];
