@@ -148,14 +148,14 @@ mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_w
 
 /* Autotuner for this context: times every fused kernel (variant 1 with
  * tile_w 64, 128 and 256, and variant 2 for a Newtonian fluid), prefetch
- * depth (2, 3; 2 with 256 lanes) and six scalings of the wall-row cost factors of the one-round
- * balanced partition over `steps` steps of the run itself, times the three
- * fastest again over 4 x `steps` steps, restores the state and step count
- * after each run (the three-pass scratch of the workspace holds the copy),
- * and keeps the fastest of the second timing.  choice
- * (host, may be NULL; 6 doubles) receives {variant, prefetch, x-wall scale,
- * y-wall scale, milliseconds per step, tile_w}.  Synchronises.  Results do
- * not depend on the choice (to rounding). */
+ * depth (2, 3; 2 with 256 lanes) and eight scalings (0.3..3.5) of the
+ * wall-row cost factors of the one-round balanced partition over `steps`
+ * steps of the run itself, times the three fastest again over 4 x `steps`
+ * steps, restores the state and step count after each run (the three-pass
+ * scratch of the workspace holds the copy), and keeps the fastest of the
+ * second timing.  choice (host, may be NULL; 6 doubles) receives {variant,
+ * prefetch, x-wall scale, y-wall scale, milliseconds per step, tile_w}.
+ * Synchronises.  Results do not depend on the choice (to rounding). */
 mdf_status mdf_autotune(mdf_ctx* ctx, int32_t steps, double* choice);
 
 /* Host-only preview of the balanced partition the fused variant (1 or 2)
