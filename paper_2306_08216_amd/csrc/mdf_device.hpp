@@ -217,12 +217,19 @@ __device__ __forceinline__ double noneq_shear_sq(const double* phi, const double
 //  n = 1/2: positive root of nu^2 - b nu - b theta = 0 with b = K^2/g, i.e.
 //           nu = (b + sqrt(b (b + 4 theta)))/2;
 //  n = 3/2: root of nu^3 + theta nu^2 - K^2 g = 0 by three Halley steps from
-//           the upper bound min(cbrt(K^2 g), sqrt(K^2 g/theta)) (nu^3 and
-//           theta nu^2 each stay below K^2 g).  The bound is within 26 % of the
-//           root for every g and theta, and Halley's cubic convergence takes
-//           that to a 1-ulp root in three steps; a fixed count keeps every lane
-//           of a wave on the same instructions.  A root beyond the clamp range
-//           is clamped like the n = 1/2 one.
+//           an upper bound of the root: nu^3 and theta nu^2 each stay below
+//           r = K^2 g, so nu <= min(r^(1/3), sqrt(r/theta)).  The cube root is
+//           read from the exponent bits: a third of r's bit pattern plus two
+//           thirds of the exponent bias is 2^(log2(r)/3) with the mantissa
+//           interpolated linearly, which overestimates r^(1/3) by 0-5.9 %.
+//           The start is then within 34 % of the root for every g and theta,
+//           and Halley's cubic convergence takes that to a 1-ulp root in three
+//           steps; a fixed count keeps every lane of a wave on the same
+//           instructions.  Each step divides by the hardware reciprocal after
+//           one Newton refinement (relative error ~1e-14 at worst), which only
+//           perturbs the correction itself; the last correction is below 1e-6
+//           of the root.  A root beyond the clamp range is clamped like the
+//           n = 1/2 one.
 __device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, double theta)
 {
     const double Kc = K.nu;
@@ -234,13 +241,18 @@ __device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, 
     } else {
         if (q == 0.0) return K.nu_min;
         const double r = Kc * Kc * sqrt(q);
-        double x = fmin(cbrt(r), sqrt(r / theta));
+        const unsigned long long rb = static_cast<unsigned long long>(__double_as_longlong(r));
+        const double cb = __longlong_as_double(static_cast<long long>(rb / 3ull + (682ull << 52)));
+        double x = fmin(cb, sqrt(r * (1.0 / theta)));
 #pragma unroll
         for (int it = 0; it < 3; ++it) {
             const double f = x * x * (x + theta) - r;
             const double d1 = x * (3.0 * x + 2.0 * theta);
             const double d2 = 6.0 * x + 2.0 * theta;
-            x -= 2.0 * f * d1 / (2.0 * d1 * d1 - f * d2);
+            const double den = 2.0 * d1 * d1 - f * d2;
+            double y = __builtin_amdgcn_rcp(den);
+            y = fma(y, fma(-den, y, 1.0), y);
+            x -= 2.0 * f * d1 * y;
         }
         nu = x;
     }
