@@ -363,3 +363,36 @@ def test_tuning_cache_round_trip(gpu, tmp_path):
     assert err <= TOL
     s.close()
     s2.close()
+
+
+@pytest.mark.parametrize("pl_n", [0.5, 1.5])
+def test_powerlaw_viscosity_over_many_decades(gpu, pl_n):
+    """The local power-law viscosity (derived plane 13) of a state whose
+    non-equilibrium parts span twelve decades, against the oracle's root of
+    nu = K (g/(nu + theta))^(n-1) at every node.  The clamp is widened to
+    [1e-12, 1] so that mostly the solve itself is compared, with nu on both
+    sides of theta (the two regimes of the n = 3/2 cubic)."""
+    import torch
+    from oracle.orc import Oracle
+
+    n = 64
+    prob = P.powerlaw_cavity(n, pl_n=pl_n)
+    prob.nu_min, prob.nu_max = 1e-12, 1.0
+    say(f"[gpu powerlaw nu] pl_n={pl_n} n={n}")
+    rng = np.random.default_rng(17)
+    mag = 10.0 ** rng.uniform(-10.0, 2.0, (1, n, n))
+    f = rng.standard_normal((10, n, n)) * mag
+    o = Oracle(prob)
+    o.set_f(f)
+    nu_o = o.derived()[13]
+    s = gpu(prob, device="cuda:0")
+    s.load(torch.from_numpy(f).to("cuda:0"))
+    nu = s.derived(1 << 13).cpu().numpy()[0]
+    s.close()
+    inside = (nu_o > prob.nu_min) & (nu_o < prob.nu_max)
+    assert inside.mean() > 0.75                        # mostly the solve, not the clamp
+    assert nu_o[inside].max() / nu_o[inside].min() > 1e4
+    theta = 0.2 * prob.c ** 2 * o.dt                   # c_s^2 dt / 2 with c_s^2 = 2c^2/5
+    assert 0.2 < (nu_o[inside] < theta).mean() < 0.8   # both regimes of the cubic
+    rel = np.abs(nu - nu_o) / nu_o
+    assert rel.max() <= 1e-13, (rel.max(), np.unravel_index(rel.argmax(), rel.shape))
