@@ -90,7 +90,8 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 @pytest.mark.parametrize("n,bc,variant,tile_w", [(1024, 1, 2, 64), (1024, 1, 1, 64), (2048, 1, 1, 64),
                                                  (1024, 0, 2, 64), (100, 1, 1, 128), (37, 0, 1, 64),
                                                  (4099, 1, 2, 64), (2048, 1, 1, 128), (2048, 1, 1, 256),
-                                                 (300, 1, 1, 256)])
+                                                 (300, 1, 1, 256), (5, 1, 1, 64), (5, 0, 2, 64),
+                                                 (6, 1, 1, 256), (9, 0, 1, 128)])
 def test_balanced_partition_covers_every_row_once(L, n, bc, variant, tile_w):
     """The launch plan of the fused step: every (strip, row) exactly once, at
     most one round of workgroups, and wall segments no taller than interior

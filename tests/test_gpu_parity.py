@@ -396,3 +396,40 @@ def test_powerlaw_viscosity_over_many_decades(gpu, pl_n):
     assert 0.2 < (nu_o[inside] < theta).mean() < 0.8   # both regimes of the cubic
     rel = np.abs(nu - nu_o) / nu_o
     assert rel.max() <= 1e-13, (rel.max(), np.unravel_index(rel.argmax(), rel.shape))
+
+
+def _smallest(nx, ny, bc_x, bc_y, seed, lid=0.0, fx=0.0, fy=0.0):
+    """A grid at the smallest size the boundary accepts (5 nodes on an axis):
+    one strip whose halo lanes wrap (periodic) or clamp (walls) many times over,
+    and segments whose row halos reach both y walls or wrap past both ends."""
+    rng = np.random.default_rng(seed)
+    u, v, p = (a * rng.standard_normal((ny, nx)) for a in (0.01, 0.01, 1e-4))
+    for w, axis in ((bc_x, 1), (bc_y, 0)):
+        if w == P.WALL:
+            for a in (u, v):
+                np.moveaxis(a, axis, 0)[[0, -1]] = 0.0
+    dx = 0.25
+    lx = dx * (nx - 1 if bc_x == P.WALL else nx)
+    ly = dx * (ny - 1 if bc_y == P.WALL else ny)
+    return P.Problem(nx=nx, ny=ny, lx=lx, ly=ly, nu=0.02, u0=u, v0=v, p0=p, bc_x=bc_x, bc_y=bc_y,
+                     lid_u=lid, fx=fx, fy=fy, name=f"smallest_{nx}x{ny}")
+
+
+SMALLEST = {
+    "cavity5x5": lambda: (_smallest(5, 5, P.WALL, P.WALL, 21, lid=0.05), 60),
+    "cavity7x6": lambda: (_smallest(7, 6, P.WALL, P.WALL, 22, lid=0.05), 60),
+    "periodic5x7": lambda: (_smallest(5, 7, P.PERIODIC, P.PERIODIC, 23), 60),
+    "periodic6x5": lambda: (_smallest(6, 5, P.PERIODIC, P.PERIODIC, 24), 60),
+    "wallx5x9": lambda: (_smallest(5, 9, P.WALL, P.PERIODIC, 25, fy=1e-4), 60),
+    "wally9x5": lambda: (_smallest(9, 5, P.PERIODIC, P.WALL, 26, fx=1e-4), 60),
+}
+CASES.update({"smallest_" + k: f for k, f in SMALLEST.items()})
+
+
+@pytest.mark.parametrize("key", sorted(SMALLEST))
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, 2, 2)), (1, (128, -1, 3)), (1, (256, -1, 2)),
+                                           (2, (0, 0)), (2, (0, 3, 3))])
+def test_smallest_grids(gpu, key, variant, shape):
+    """Degenerate sizes: 5 to 9 nodes per axis, every boundary combination,
+    every kernel variant and tile width, element by element against the oracle."""
+    _compare("smallest_" + key, gpu, variant, shape)
