@@ -149,3 +149,22 @@ def test_batch_validation_without_device_work(L):
     assert L.lib().mdf_batch_step(None, 1) == L.MDF_EINVAL
     assert L.lib().mdf_batch_set_kernel(None, 1, 64, 2, 1) == L.MDF_EINVAL
     L.lib().mdf_batch_destroy(None)
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(32768, 6, 0), (32768, 5, 1), (6, 32768, 1), (5, 32768, 0)])
+@pytest.mark.parametrize("variant,tile_w", [(1, 64), (1, 256), (2, 64)])
+def test_partition_at_maximum_extent(L, nx, ny, bc, variant, tile_w):
+    """The launch plan at the largest extent the boundary accepts on one axis:
+    every (strip, row) exactly once, within the segment table."""
+    p, keep = _params(L, nx=nx, ny=ny, bc_x=bc, bc_y=bc)
+    segs = L.mdf_plan_segments(p, variant, tile_w, 1024)
+    assert segs and len(segs) <= 4096
+    nstrips = -(-nx // (tile_w - 8))
+    cover = {}
+    for s, y0, y1 in segs:
+        assert 0 <= s < nstrips and 0 <= y0 < y1 <= ny
+        cover.setdefault(s, []).append((y0, y1))
+    assert sorted(cover) == list(range(nstrips))
+    for iv in cover.values():
+        iv.sort()
+        assert iv[0][0] == 0 and iv[-1][1] == ny and all(a[1] == b[0] for a, b in zip(iv, iv[1:]))

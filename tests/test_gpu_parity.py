@@ -433,3 +433,20 @@ def test_smallest_grids(gpu, key, variant, shape):
     """Degenerate sizes: 5 to 9 nodes per axis, every boundary combination,
     every kernel variant and tile width, element by element against the oracle."""
     _compare("smallest_" + key, gpu, variant, shape)
+
+
+EXTENT = {
+    "wide32768x6": lambda: (_smallest(32768, 6, P.PERIODIC, P.PERIODIC, 31), 12),
+    "widecavity32768x5": lambda: (_smallest(32768, 5, P.WALL, P.WALL, 32, lid=0.05), 12),
+    "tall6x32768": lambda: (_smallest(6, 32768, P.WALL, P.PERIODIC, 33, fy=1e-4), 12),
+}
+CASES.update({"extent_" + k: f for k, f in EXTENT.items()})
+
+
+@pytest.mark.parametrize("key", sorted(EXTENT))
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, -1, 2)), (1, (256, -1, 2)), (2, (0, 0))])
+def test_maximum_extent(gpu, key, variant, shape):
+    """The largest extent the boundary accepts on one axis (32768 nodes) with
+    the smallest on the other: hundreds of strips across one row, or one strip
+    down thousands of rows, element by element against the oracle."""
+    _compare("extent_" + key, gpu, variant, shape)
