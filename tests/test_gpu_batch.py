@@ -185,3 +185,51 @@ def test_full_batch_config_sampled(gpu):
         say(f"    instance {i} n={probs[i].nx} nu={probs[i].nu:.3g} max|df|={err:.3e}")
         assert err <= TOL
     b.close()
+
+
+def _tiny(nx, ny, seed, nu):
+    rng = np.random.default_rng(seed)
+    u, v, p = (a * rng.standard_normal((ny, nx)) for a in (0.01, 0.01, 1e-4))
+    return P.Problem(nx=nx, ny=ny, lx=0.25 * nx, ly=0.25 * ny, nu=nu, u0=u, v0=v, p0=p, name=f"tiny_{nx}x{ny}")
+
+
+DEGENERATE = {
+    "single": lambda: [P.random_vortex(48, 900, 0.004, kmax=5, urms=0.03)],
+    "smallest": lambda: [_tiny(5, 5, 41, 0.02), _tiny(5, 7, 42, 0.01), _tiny(7, 5, 43, 0.05),
+                         _tiny(6, 6, 44, 0.02), _tiny(9, 5, 45, 0.03),
+                         P.random_vortex(64, 46, 0.005, kmax=5, urms=0.03)],
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _degenerate_oracle(key, steps):
+    from oracle.orc import Oracle
+    out = []
+    for p in DEGENERATE[key]():
+        o = Oracle(p)
+        o.step(steps)
+        out.append(o.f())
+    return out
+
+
+@pytest.mark.parametrize("key", sorted(DEGENERATE))
+@pytest.mark.parametrize("variant,prefetch,rounds,tile_w", [(1, 2, 1, 64), (1, 3, 2, 128), (1, 2, 1, 256), (2, 2, 1, 64)])
+def test_batch_degenerate(gpu, key, variant, prefetch, rounds, tile_w):
+    """A batch of one instance, and instances of the smallest size the boundary
+    accepts (5 nodes on an axis) beside a larger one, each against its own
+    oracle run."""
+    probs = DEGENERATE[key]()
+    steps = 40
+    say(f"[gpu batch] {key} sizes={[(p.nx, p.ny) for p in probs]} steps={steps} "
+        f"variant={variant} prefetch={prefetch} rounds={rounds} tile_w={tile_w}")
+    want = _degenerate_oracle(key, steps)
+    b = gpu(probs)
+    b.set_kernel(variant, prefetch, rounds, tile_w)
+    b.step(steps)
+    b.synchronize()
+    for i, p in enumerate(probs):
+        f = b.save(i).cpu().numpy()
+        err = np.abs(f - want[i]).max()
+        say(f"    instance {i} {p.nx}x{p.ny} max|df|={err:.3e}")
+        assert np.all(np.isfinite(f)) and err <= TOL
+    b.close()
