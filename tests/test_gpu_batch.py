@@ -233,3 +233,19 @@ def test_batch_degenerate(gpu, key, variant, prefetch, rounds, tile_w):
         say(f"    instance {i} {p.nx}x{p.ny} max|df|={err:.3e}")
         assert np.all(np.isfinite(f)) and err <= TOL
     b.close()
+
+
+def test_batch_zero_steps_keep_the_initial_state(gpu):
+    """Stepping a batch by zero leaves every instance at its initial equilibrium."""
+    from oracle.orc import Oracle
+    probs = DEGENERATE["smallest"]()
+    say(f"[gpu batch] zero steps sizes={[(p.nx, p.ny) for p in probs]}")
+    b = gpu(probs)
+    b.step(0)
+    b.synchronize()
+    assert b.steps == 0
+    for i, p in enumerate(probs):
+        err = np.abs(b.save(i).cpu().numpy() - Oracle(p).f()).max()
+        say(f"    instance {i} {p.nx}x{p.ny} max|df|={err:.3e}")
+        assert err <= TOL
+    b.close()
