@@ -218,7 +218,8 @@ def test_stretched_cavity_interior_segments(gpu, key, variant, shape):
     _compare(key, gpu, variant, shape)
 
 
-@pytest.mark.parametrize("key", ["tg64", "cavity128", "plcav_n0.5", "plcav_n1.5"])
+@pytest.mark.parametrize("key", ["tg64", "cavity128", "plcav_n0.5", "plcav_n1.5", "smallest_cavity5x5",
+                                 "smallest_periodic5x7", "smallest_wally9x5", "extent_wide32768x6"])
 def test_derived_and_diagnostics(gpu, key):
     """mdf_derived (eqs. 2.4.1-2.4.5, all 14 planes) and mdf_diagnostics against the oracle."""
     o, prob, steps = oracle_run(key)
