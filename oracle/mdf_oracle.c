@@ -9,6 +9,10 @@
  * matrices exactly as the equations write them (the paper's "2 x 5 x 5"
  * cycles of Sec. 4.2); nothing is fused or reordered.
  *
+ * The OpenMP build of this same file runs the node loops of each sub-step in
+ * parallel; every node of a sub-step only reads the previous sub-step's
+ * arrays, so the results are identical to the sequential build.
+ *
  * Readings taken where the paper is silent or garbled:
  *  - c_s^2 follows from the second-moment condition of eq. 2.3.4 with w_j = 1/5;
  *  - the MRT matrix is M^-1 diag(s',s,s,s',s') M with an orthogonal D2Q5 basis;
@@ -25,6 +29,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NQ 5
 #define NPL 10
@@ -40,6 +47,7 @@ struct orc_state {
     size_t n;
     double c, cs2, dt, h;
     double *gx, *gy;          /* derivative scale 1/(X' dxi) at each node */
+    double *Fx, *Fy;          /* body force F_alpha at each node (eq. 2.2.6) */
     double *fhat;             /* state f_hat(t)            */
     double *fhat_plus;        /* f_hat^+(t)   (eq. 2.2.14) */
     double *fbar_plus;        /* f_bar^+(t)   (eq. 2.2.15) */
@@ -451,11 +459,12 @@ static void collide_step3(const orc_state* st, const double* fbar, double* f)
 static void one_step(orc_state* st)
 {
     int nx = st->nx, ny = st->ny;
-    size_t n = st->n;
-    double Fa[2] = {st->p.fx, st->p.fy};
+    long n = (long)st->n;
+    const double* Fa[2] = {st->Fx, st->Fy};
 
     /* Step (1): f_hat^+ and f_bar^+ at every node. */
-    for (size_t i = 0; i < n; ++i) {
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
         double fh[NPL], fhp[NPL], fbp[NPL];
         gather(st, st->fhat, i, fh);
         orc_collide_step1(st, fh, fhp, fbp);
@@ -465,7 +474,9 @@ static void one_step(orc_state* st)
     orc_wall_update(st, st->fbar_plus);
 
     /* Step (2): f_bar(t+h) = f_bar^+ - h c_j . grad f_bar^+ + h w_j F_alpha
-     * (eq. 2.2.11 with the O(h^2) and G terms dropped per Remark 2, eq. 2.2.6). */
+     * (eq. 2.2.11 with the O(h^2) and G terms dropped per Remark 2, eq. 2.2.6;
+     * the force is steady, so its time derivative vanishes). */
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (is_wall(st, x, y)) continue;
@@ -474,11 +485,12 @@ static void one_step(orc_state* st)
                 for (int j = 0; j < NQ; ++j) {
                     const double* pl = st->fbar_plus + (size_t)(a * NQ + j) * n;
                     st->fbar[(size_t)(a * NQ + j) * n + i] =
-                        pl[i] - st->h * cdotgrad(st, pl, x, y, j) + st->h * WJ[j] * Fa[a];
+                        pl[i] - st->h * cdotgrad(st, pl, x, y, j) + st->h * WJ[j] * Fa[a][i];
                 }
         }
 
     /* Step (3): f(t+h) from f_bar(t+h) at every non-wall node, walls by rule. */
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (is_wall(st, x, y)) continue;
@@ -492,6 +504,7 @@ static void one_step(orc_state* st)
 
     /* Step (4): f_hat(t+dt) = f_hat^+ - dt c_j . grad f(t+h) + dt w_j F_alpha
      * (eq. 2.3.24; the dt^2/2 d_t F term vanishes for a steady force). */
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (is_wall(st, x, y)) continue;
@@ -501,7 +514,7 @@ static void one_step(orc_state* st)
                     size_t k = (size_t)(a * NQ + j) * n;
                     st->fnew[k + i] = st->fhat_plus[k + i]
                                     - st->dt * cdotgrad(st, st->fmid + k, x, y, j)
-                                    + st->dt * WJ[j] * Fa[a];
+                                    + st->dt * WJ[j] * Fa[a][i];
                 }
         }
     orc_wall_update(st, st->fnew);
@@ -515,6 +528,17 @@ static void one_step(orc_state* st)
 void orc_step(orc_state* st, int32_t nsteps)
 {
     for (int32_t s = 0; s < nsteps; ++s) one_step(st);
+}
+
+int32_t orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------ */
@@ -543,6 +567,15 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     double hy = p->bc_y == ORC_WALL ? p->ly / (p->ny - 1) : p->ly / p->ny;
     st->gx = (double*)malloc(sizeof(double) * p->nx);
     st->gy = (double*)malloc(sizeof(double) * p->ny);
+    /* body force per node: the uniform part plus the optional field */
+    st->Fx = (double*)malloc(sizeof(double) * st->n);
+    st->Fy = (double*)malloc(sizeof(double) * st->n);
+    for (size_t i = 0; i < st->n; ++i) {
+        st->Fx[i] = p->fx + (p->force_x ? p->force_x[i] : 0.0);
+        st->Fy[i] = p->fy + (p->force_y ? p->force_y[i] : 0.0);
+    }
+    st->p.force_x = NULL;
+    st->p.force_y = NULL;
     for (int i = 0; i < p->nx; ++i) st->gx[i] = p->inv_dx_x ? p->inv_dx_x[i] : 1.0 / hx;
     for (int i = 0; i < p->ny; ++i) st->gy[i] = p->inv_dx_y ? p->inv_dx_y[i] : 1.0 / hy;
     double dxmin = (p->inv_dx_x || p->inv_dx_y) ? p->dx_min : (hx < hy ? hx : hy);
@@ -580,6 +613,8 @@ void orc_destroy(orc_state* st)
     if (!st) return;
     free(st->gx);
     free(st->gy);
+    free(st->Fx);
+    free(st->Fy);
     free(st->fhat);
     free(st->fhat_plus);
     free(st->fbar_plus);

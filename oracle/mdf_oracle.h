@@ -39,6 +39,8 @@ typedef struct {
     const double* inv_dx_x;  /* nx entries: d(xi)/dx / d(xi), i.e. 1/(X'(xi_i) dxi); NULL = uniform */
     const double* inv_dx_y;  /* ny entries, same meaning for y                        */
     double  dx_min;          /* smallest node spacing; used for dt when metrics are given */
+    const double* force_x;   /* ny*nx entries added to fx at each node (steady F(x), eq. 2.2.6); NULL = none */
+    const double* force_y;   /* same for fy                                           */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -59,6 +61,8 @@ void       orc_moments(const orc_state* st, double* u, double* v, double* p);
 void       orc_derived(const orc_state* st, double* out);
 /* 8 scalars: sum u, sum v, KE, enstrophy, max|u|, max|FD div u|, non-finite count, area */
 void       orc_diagnostics(const orc_state* st, double* out);
+/* threads of the OpenMP build (no effect in the sequential build); returns the count in use */
+int32_t    orc_set_threads(int32_t n);
 
 /* ---- pieces exposed so that tests can pin them one by one ---- */
 /* f^eq for one node (eq. 2.2.5): out[alpha*5+j] */

@@ -5,6 +5,7 @@ product path never imports it.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 from typing import Optional
@@ -13,6 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
+LIB_OMP_PATH = os.path.join(HERE, "liborc_omp.so")
 
 _dp = C.POINTER(C.c_double)
 
@@ -29,19 +31,42 @@ class OrcParams(C.Structure):
         ("fx", C.c_double), ("fy", C.c_double),
         ("inv_dx_x", _dp), ("inv_dx_y", _dp),
         ("dx_min", C.c_double),
+        ("force_x", _dp), ("force_y", _dp),
     ]
 
 
-_lib = None
+_libs = {}
+_override = None
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(kind: str = "serial"):
+    """The oracle library: "serial" (liborc.so) or "omp" (liborc_omp.so, the
+    same sources with OpenMP over the node loops).  Inside using_library()
+    every kind resolves to that library."""
+    path = _override or (LIB_OMP_PATH if kind == "omp" else LIB_PATH)
+    if path not in _libs:
+        if not os.path.exists(path):
             from oracle import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
+        _libs[path] = _declare(C.CDLL(path))
+    return _libs[path]
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every oracle call made inside the block (and by Oracle objects
+    created inside it) to the library at `path` (a differently built copy of
+    the oracle sources, e.g. one with a planted mistake)."""
+    global _override
+    old = _override
+    _override = os.path.abspath(path)
+    try:
+        yield lib()
+    finally:
+        _override = old
+
+
+def _declare(L):
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(OrcParams), _dp, _dp, _dp]
         L.orc_destroy.argtypes = [C.c_void_p]
@@ -71,8 +96,9 @@ def lib():
         L.orc_wall_update.argtypes = [C.c_void_p, _dp]
         L.orc_powerlaw_nu.restype = C.c_double
         L.orc_powerlaw_nu.argtypes = [C.c_void_p, C.c_double, C.c_double]
-        _lib = L
-    return _lib
+        L.orc_set_threads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
+        return L
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -86,23 +112,35 @@ def _params(prob):
     keep = []
     gx = None if prob.inv_dx_x is None else np.ascontiguousarray(prob.inv_dx_x, dtype=np.float64)
     gy = None if prob.inv_dx_y is None else np.ascontiguousarray(prob.inv_dx_y, dtype=np.float64)
-    keep += [gx, gy]
+    ffx = getattr(prob, "force_x", None)
+    ffy = getattr(prob, "force_y", None)
+    ffx = None if ffx is None else np.ascontiguousarray(ffx, dtype=np.float64)
+    ffy = None if ffy is None else np.ascontiguousarray(ffy, dtype=np.float64)
+    for a in (ffx, ffy):
+        assert a is None or a.shape == (prob.ny, prob.nx)
+    keep += [gx, gy, ffx, ffy]
     p = OrcParams(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                   prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
-                  prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min)
+                  prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min, _ptr(ffx), _ptr(ffy))
     return p, keep
 
 
 class Oracle:
-    """One oracle run of a problems.Problem."""
+    """One oracle run of a problems.Problem.  threads > 0 runs it on the OpenMP
+    build with that many threads (results identical to the sequential build)."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, threads: int = 0):
         self.prob = prob
+        self._L = lib("omp" if threads > 0 else "serial")
+        if threads > 0:
+            self.threads = self._L.orc_set_threads(int(threads))
+        else:
+            self.threads = 1
         self._p, self._keep = _params(prob)
         u0 = np.ascontiguousarray(prob.u0, dtype=np.float64)
         v0 = np.ascontiguousarray(prob.v0, dtype=np.float64)
         p0 = np.ascontiguousarray(prob.p0, dtype=np.float64)
-        self._h = lib().orc_create(C.byref(self._p), _ptr(u0), _ptr(v0), _ptr(p0))
+        self._h = self._L.orc_create(C.byref(self._p), _ptr(u0), _ptr(v0), _ptr(p0))
         if not self._h:
             raise ValueError("oracle rejected the problem parameters")
         self.nx, self.ny = prob.nx, prob.ny
@@ -110,7 +148,7 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._L.orc_destroy(h)
             self._h = None
 
     @property
@@ -119,69 +157,69 @@ class Oracle:
 
     @property
     def dt(self) -> float:
-        return lib().orc_dt(self._h)
+        return self._L.orc_dt(self._h)
 
     @property
     def steps(self) -> int:
-        return lib().orc_steps(self._h)
+        return self._L.orc_steps(self._h)
 
     def step(self, n: int = 1):
-        lib().orc_step(self._h, int(n))
+        self._L.orc_step(self._h, int(n))
         return self
 
     def f(self) -> np.ndarray:
         out = np.empty((10, self.ny, self.nx))
-        lib().orc_get_f(self._h, _ptr(out))
+        self._L.orc_get_f(self._h, _ptr(out))
         return out
 
     def set_f(self, f: np.ndarray):
         f = np.ascontiguousarray(f, dtype=np.float64)
         assert f.shape == (10, self.ny, self.nx)
-        lib().orc_set_f(self._h, _ptr(f))
+        self._L.orc_set_f(self._h, _ptr(f))
 
     def fields(self, which: int) -> np.ndarray:
         """Intermediate field of the last step: 0 f_hat^+, 1 f_bar^+, 2 f_bar(t+h), 3 f(t+h)."""
         out = np.empty((10, self.ny, self.nx))
-        lib().orc_fields(self._h, int(which), _ptr(out))
+        self._L.orc_fields(self._h, int(which), _ptr(out))
         return out
 
     def moments(self):
         u = np.empty((self.ny, self.nx))
         v = np.empty_like(u)
         p = np.empty_like(u)
-        lib().orc_moments(self._h, _ptr(u), _ptr(v), _ptr(p))
+        self._L.orc_moments(self._h, _ptr(u), _ptr(v), _ptr(p))
         return u, v, p
 
     def derived(self) -> np.ndarray:
         out = np.empty((14, self.ny, self.nx))
-        lib().orc_derived(self._h, _ptr(out))
+        self._L.orc_derived(self._h, _ptr(out))
         return out
 
     def diagnostics(self) -> np.ndarray:
         out = np.empty(8)
-        lib().orc_diagnostics(self._h, _ptr(out))
+        self._L.orc_diagnostics(self._h, _ptr(out))
         return out
 
     def mixed_derivative(self, plane: np.ndarray, axis: int, sign: int) -> np.ndarray:
         plane = np.ascontiguousarray(plane, dtype=np.float64)
         out = np.empty_like(plane)
-        lib().orc_mixed_derivative(self._h, _ptr(plane), axis, sign, _ptr(out))
+        self._L.orc_mixed_derivative(self._h, _ptr(plane), axis, sign, _ptr(out))
         return out
 
     def wall_update(self, field: np.ndarray) -> np.ndarray:
         field = np.array(field, dtype=np.float64, order="C", copy=True)
-        lib().orc_wall_update(self._h, _ptr(field))
+        self._L.orc_wall_update(self._h, _ptr(field))
         return field
 
     def collide_step1(self, fhat_node: np.ndarray):
         fh = np.ascontiguousarray(fhat_node, dtype=np.float64)
         a = np.empty(10)
         b = np.empty(10)
-        lib().orc_collide_step1(self._h, _ptr(fh), _ptr(a), _ptr(b))
+        self._L.orc_collide_step1(self._h, _ptr(fh), _ptr(a), _ptr(b))
         return a, b
 
     def powerlaw_nu(self, gam_hat: float, theta: float) -> float:
-        return lib().orc_powerlaw_nu(self._h, gam_hat, theta)
+        return self._L.orc_powerlaw_nu(self._h, gam_hat, theta)
 
 
 def feq(c: float, u: float, v: float, P: float) -> np.ndarray:

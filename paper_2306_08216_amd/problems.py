@@ -53,6 +53,8 @@ class Problem:
     inv_dx_x: Optional[np.ndarray] = None
     inv_dx_y: Optional[np.ndarray] = None
     dx_min: float = 0.0
+    force_x: Optional[np.ndarray] = None   # (ny, nx) steady force field added to fx (None: none)
+    force_y: Optional[np.ndarray] = None   # (ny, nx) added to fy
     name: str = ""
 
     @property
@@ -101,6 +103,68 @@ def taylor_green_exact(prob: Problem, t: float, u0: float, nu: float):
     v = -u0 * dec * np.cos(k * X) * np.sin(k * Y)
     p = 0.25 * u0 * u0 * dec * dec * (np.cos(2 * k * X) + np.cos(2 * k * Y))
     return u, v, p
+
+
+def four_roll_mill(n: int = 64, u0: float = 1e-4, nu: float = 0.01, cfl: float = 0.5, eta: float = 0.8,
+                   s_ratio: float = 1.5, start: str = "exact", printed_sign: bool = False) -> Problem:
+    """Four-roll mill (Sec. 4.1): periodic [0, 2pi]^2 driven by the steady force of
+    eq. 4.1.1, whose steady solution is eq. 4.1.2, u = U0 sin x cos y,
+    v = -U0 sin y cos x, with uniform pressure.  The viscous part of F_2 is
+    taken as -2 nu U0 sin y cos x, the sign the Laplacian of v requires (the
+    printed + sign, printed_sign=True, does not balance eq. 4.1.2).  start:
+    "exact" (f_hat = f^eq of eq. 4.1.2) or "rest"."""
+    L = 2.0 * math.pi
+    x = _axis_nodes(n, L, PERIODIC)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    sgn = 1.0 if printed_sign else -1.0
+    fx = u0 * u0 * np.sin(X) * np.cos(X) + 2.0 * nu * u0 * np.sin(X) * np.cos(Y)
+    fy = u0 * u0 * np.sin(Y) * np.cos(Y) + sgn * 2.0 * nu * u0 * np.sin(Y) * np.cos(X)
+    if start == "exact":
+        u, v = u0 * np.sin(X) * np.cos(Y), -u0 * np.sin(Y) * np.cos(X)
+    else:
+        u, v = np.zeros((n, n)), np.zeros((n, n))
+    return Problem(nx=n, ny=n, lx=L, ly=L, nu=nu, u0=u, v0=v, p0=np.zeros((n, n)), cfl=cfl, eta=eta,
+                   s_ratio=s_ratio, force_x=fx, force_y=fy, name=f"four_roll_mill_{n}")
+
+
+def four_roll_mill_exact(prob: Problem, u0: float = 1e-4):
+    """Eq. 4.1.2 and eq. 4.1.3 at the nodes: dict of u, v, ux, uy, vx, vy, Sxx,
+    Sxy, Syy, omega, Omega_xy."""
+    X, Y = np.meshgrid(prob.node_x(), prob.node_y(), indexing="xy")
+    c, ss = u0 * np.cos(X) * np.cos(Y), u0 * np.sin(X) * np.sin(Y)
+    return {"u": u0 * np.sin(X) * np.cos(Y), "v": -u0 * np.sin(Y) * np.cos(X), "ux": c, "uy": -ss,
+            "vx": ss, "vy": -c, "Sxx": c, "Sxy": 0.0 * c, "Syy": -c, "omega": 2.0 * ss, "Omega_xy": -ss}
+
+
+def periodic_flow(nx: int = 32, ny: Optional[int] = None, u0: float = 0.1, nu: float = 0.01, cfl: float = 0.5,
+                  eta: float = 0.8, s_ratio: float = 1.5, inv_dx_x: Optional[np.ndarray] = None,
+                  x_nodes: Optional[np.ndarray] = None, dx_min: float = 0.0) -> Problem:
+    """Steady periodic flow (Sec. 4.2) on [0, 1]^2 with the force of eq. 4.2.1,
+    F_x = 8 pi^2 nu u0 sin 2pi x sin 2pi y, F_y = 8 pi^2 nu u0 cos 2pi x cos 2pi y,
+    started from its steady solution eq. 4.2.2 (f_hat = f^eq).  ny != nx gives
+    the rectangular-cell grid (e.g. 64 x 32); inv_dx_x with its node
+    positions x_nodes maps the x axis."""
+    ny = nx if ny is None else ny
+    x = _axis_nodes(nx, 1.0, PERIODIC) if x_nodes is None else np.asarray(x_nodes, dtype=np.float64)
+    y = _axis_nodes(ny, 1.0, PERIODIC)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    k = 2.0 * math.pi
+    amp = 8.0 * math.pi ** 2 * nu * u0
+    fx = amp * np.sin(k * X) * np.sin(k * Y)
+    fy = amp * np.cos(k * X) * np.cos(k * Y)
+    u = u0 * np.sin(k * X) * np.sin(k * Y)
+    v = u0 * np.cos(k * X) * np.cos(k * Y)
+    p = 0.25 * u0 * u0 * (np.cos(2 * k * X) - np.cos(2 * k * Y))
+    return Problem(nx=nx, ny=ny, lx=1.0, ly=1.0, nu=nu, u0=u, v0=v, p0=p, cfl=cfl, eta=eta, s_ratio=s_ratio,
+                   force_x=fx, force_y=fy, inv_dx_x=inv_dx_x, dx_min=dx_min, name=f"periodic_flow_{nx}x{ny}")
+
+
+def periodic_flow_exact(x: np.ndarray, y: np.ndarray, u0: float = 0.1):
+    """Eq. 4.2.2 at nodes x (columns) and y (rows): u, v, p."""
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    k = 2.0 * math.pi
+    return (u0 * np.sin(k * X) * np.sin(k * Y), u0 * np.cos(k * X) * np.cos(k * Y),
+            0.25 * u0 * u0 * (np.cos(2 * k * X) - np.cos(2 * k * Y)))
 
 
 def cavity(n: int = 1024, re: float = 1000.0, lid: float = 0.1, cfl: float = 0.5, eta: float = 0.8,
