@@ -1,19 +1,30 @@
 """Benchmark of the MDF-FDLBM FP64 time step on one MI355X.
 
-Workload: lid-driven square cavity, Re = 1000, 1024 x 1024 nodes (walls
-included), lid speed 0.1, fluid at rest initially, FP64 throughout.  A "step"
-is one full time step of the method (Steps (1)-(4) of Sec. 2.2 with walls).
+Default workload: the power-law lid-driven cavity on a tanh-stretched
+2048 x 2048 grid (beta = 1.5 on both axes, Re_PL = 100, lid speed 0.1, FP64),
+for both power-law indices n = 0.5 and n = 1.5.  Each index starts from a
+state pre-run from rest (the input state of the workload: the lid has sheared
+the corners, where the local viscosity reaches its clamp).  A "step" is one
+full time step of the method (Steps (1)-(4) of Sec. 2.2 with walls and the
+local power-law viscosity) for each of the two indices, so one step updates
+2 x 2048^2 nodes.
 
-Prints one JSON line with MLUPS (= nodes x steps / s / 1e6), the roofline of
-the fused step kernel (algorithmic 160 B per node and step: one read and one
-write of the ten FP64 distribution planes) and the CPU oracle timed on a
-bounded sample of the same workload.
+Timing: after the warm-up steps, exactly --steps steps per index are timed
+with HIP events on the solver's stream, as five consecutive regions; the
+median region gives the time per step.  The line reports MLUPS, the roofline
+of the step kernel (algorithmic 160 B per node and step: one read and one
+write of the ten FP64 distribution planes) beside the rate of a plain
+streaming copy measured in the same run, and the CPU oracle timed on a
+bounded sample of the same workload, on one thread and on all host cores.
+A run whose state holds a non-finite value prints an error line and exits
+with status 3.
 """
 import argparse
 import hashlib
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -26,17 +37,26 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2306_08216_amd", "csrc")
 TUNING = os.path.join(ROOT, "paper_2306_08216_amd", "tuning_mi355x.json")
 METRIC = "MLUPS (FP64) + % HBM roofline; learned-closure speedup at equal L2 error"
+REGIONS = 5
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def step_sources():
+    """The files that define the step kernels and their launch plan."""
+    names = sorted(f for f in os.listdir(CSRC) if f.startswith("mdf_fused") or f in (
+        "mdf_device.hpp", "mdf_internal.hpp", "mdf_api.hip"))
+    return names
+
+
 def kernel_sha():
     """Digest of the step's sources (kernels, device header, launch plan); a
     counter summary taken on other sources no longer describes these kernels."""
     h = hashlib.sha256()
-    for f in ("mdf_fused.hip", "mdf_fused2.hip", "mdf_device.hpp", "mdf_internal.hpp", "mdf_api.hip"):
+    for f in step_sources():
+        h.update(f.encode())
         h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -47,114 +67,104 @@ def choice_text(choice):
     return f"{int(v)} {int(tw)} {int(pf)} {float(sx):g} {float(sy):g}"
 
 
-def measured_traffic(workload, n, choice):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of this
-    workload, if it was taken on the current sources with the same kernel
-    choice; else None."""
-    path = os.path.join(PROFILES, f"fused_step_{workload}{n}_traffic.md")
-    if choice is None or not os.path.exists(path):
-        return None
-    txt = open(path).read()
-    m_sha = re.search(r"kernel_sha:\s*([0-9a-f]+)", txt)
-    m_ch = re.search(r"choice:\s*([^\n]+)", txt)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not (m_sha and m_ch and m_b) or m_sha.group(1) != kernel_sha() or m_ch.group(1).strip() != choice_text(choice):
-        return None
-    return float(m_b.group(1))
-
-
-def measured_batch_traffic(choice):
-    """HBM bytes per batched step from the committed counter summary, if taken
-    on the current sources with the same (variant, prefetch, rounds, tile_w)."""
-    path = os.path.join(PROFILES, "fused_step_batch256_traffic.md")
+def _summary_bytes(path, want_choice):
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_sha = re.search(r"kernel_sha:\s*([0-9a-f]+)", txt)
     m_ch = re.search(r"choice:\s*([^\n]+)", txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    want = " ".join(str(int(v)) for v in choice)
-    if not (m_sha and m_ch and m_b) or m_sha.group(1) != kernel_sha() or m_ch.group(1).strip() != want:
+    if not (m_sha and m_ch and m_b) or m_sha.group(1) != kernel_sha() or m_ch.group(1).strip() != want_choice:
         return None
     return float(m_b.group(1))
 
 
-def cpu_baseline(prob, steps):
-    """The CPU oracle (single thread, as it stands) on `steps` steps of the same workload."""
-    from oracle.orc import Oracle
-    o = Oracle(prob)
-    o.step(1)
-    t0 = time.perf_counter()
-    o.step(steps)
-    el = time.perf_counter() - t0
-    return prob.nodes * steps / el / 1e6, el
+def measured_traffic(workload, n, choice):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    workload, if it was taken on the current sources with the same kernel
+    choice; else None."""
+    if choice is None:
+        return None
+    return _summary_bytes(os.path.join(PROFILES, f"fused_step_{workload}{n}_traffic.md"), choice_text(choice))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=1024, help="nodes per side")
-    ap.add_argument("--workload", choices=["cavity", "taylor-green", "powerlaw", "batch"], default="cavity",
-                    help="cavity: the benchmarked lid-driven cavity; taylor-green: periodic decaying "
-                         "vortex of the same size (wall-free comparison); powerlaw: power-law cavity "
-                         "(n = 0.5) on a tanh-stretched grid; batch: 256 periodic decaying-vortex instances "
-                         "of sizes 64..512 advanced together (one launch per step)")
-    ap.add_argument("--pl-n", type=float, default=0.5, choices=[0.5, 1.5],
-                    help="power-law index of the powerlaw workload")
-    ap.add_argument("--tile-w", type=int, default=0)
-    ap.add_argument("--seg-h", type=int, default=0,
-                    help="rows per segment; -r: the balanced plan over r rounds of workgroups (0: library default)")
-    ap.add_argument("--variant", type=int, default=-1,
-                    help="step kernel: 0 three-pass, 1 fused one wave per strip, 2 fused one wave per "
-                         "velocity component (-1: the library's default for the workload)")
-    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps for the CPU baseline (0 = skip)")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the library's autotuner (run before the warm-up, outside the timed region)")
-    ap.add_argument("--tuning", default=TUNING,
-                    help="tuning cache: a kernel choice stored for this workload and device is used as is; "
-                         "otherwise the autotuner runs and its choice is stored")
-    ap.add_argument("--retune", action="store_true", help="run the autotuner even if the cache holds a choice")
-    ap.add_argument("--prefetch", type=int, default=0, help="rows prefetched by the fused kernel (2 or 3)")
-    ap.add_argument("--cost-scales", default="",
-                    help="x,y scalings of the wall-row costs in the balanced partition (instead of autotuning)")
-    ap.add_argument("--copy-calib", type=int, default=0,
-                    help="after timing, run this many plain state copies (mdf_save: 80 B read + 80 B written "
-                         "per node) as the known-size reference for HBM byte counters")
-    args = ap.parse_args()
+def measured_batch_traffic(choice):
+    """HBM bytes per batched step from the committed counter summary, if taken
+    on the current sources with the same (variant, prefetch, rounds, tile_w)."""
+    return _summary_bytes(os.path.join(PROFILES, "fused_step_batch256_traffic.md"),
+                          " ".join(str(int(v)) for v in choice))
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "the MDF-FDLBM step runs on exactly one GPU here; multi-GPU runs are not supported",
-                          "n_gpus": args.gpus}), flush=True)
-        sys.exit(2)
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_regions(run, stream, steps, regions=REGIONS):
+    """Time exactly `steps` steps as `regions` consecutive event-bracketed
+    regions on `stream`; returns the milliseconds per step of each region."""
     import torch
+    counts = [steps // regions + (1 if r < steps % regions else 0) for r in range(regions)]
+    counts = [c for c in counts if c > 0]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(counts) + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for r, c in enumerate(counts):
+        run(c)
+        ev[r + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[r].elapsed_time(ev[r + 1]) / c for r, c in enumerate(counts)]
 
-    from paper_2306_08216_amd import problems as P
+
+def copy_ceiling(nbytes, reps=20):
+    """Rate of the library's streaming copy (16-byte loads and stores) moving
+    nbytes read + nbytes written, median of five regions: the practical HBM
+    ceiling beside which the step's bandwidth is read."""
+    import torch
+    from paper_2306_08216_amd import _lib as L
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        L.mdf_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, stream.cuda_stream)
+    ms = time_regions(lambda c: [L.mdf_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, stream.cuda_stream)
+                                 for _ in range(c)], stream, reps * REGIONS)
+    med = statistics.median(ms)
+    del a, b
+    return {"GB/s": round(2 * nbytes / (med / 1e3) / 1e9, 1), "bytes_per_copy": 2 * nbytes, "us": round(med * 1e3, 2),
+            "kernel": "k_stream_copy (mdf_stream_copy)"}
+
+
+def diag_summary(diag, status):
+    return {"status": int(status), "ke": float(diag[2]), "max_speed": float(diag[4]), "nonfinite": int(diag[6])}
+
+
+def diverged(diag, status):
+    import math
+    return status != 0 or not all(math.isfinite(float(x)) for x in diag)
+
+
+def fail_diverged(what, diag, status):
+    print(json.dumps({"error": f"non-finite state after the timed steps ({what}); no throughput reported",
+                      "diagnostics": diag_summary(diag, status)}), flush=True)
+    sys.exit(3)
+
+
+def run_solver(prob, args, label, prerun, want_state=False):
+    """Set up one run, pre-run and warm it up, take the kernel choice (tuning
+    cache or autotuner, outside the timing), time exactly args.steps steps.
+    Returns a dict of results (and the state before the timed steps)."""
+    import torch
     from paper_2306_08216_amd.solver import Solver
-
-    if args.workload == "batch":
-        return bench_batch(args)
-
-    if args.workload == "cavity":
-        prob = P.cavity(args.n, re=1000.0, lid=0.1)
-        wl = f"lid-driven cavity Re=1000, {args.n}x{args.n} nodes, lid 0.1, from rest, FP64"
-    elif args.workload == "powerlaw":
-        prob = P.powerlaw_cavity(args.n, pl_n=args.pl_n)
-        wl = f"power-law cavity n={args.pl_n:g}, tanh-stretched {args.n}x{args.n} grid, Re_PL=100, lid 0.1, FP64"
-    else:
-        prob = P.taylor_green(args.n, u0=0.01, nu=0.01)
-        wl = f"periodic Taylor-Green vortex, {args.n}x{args.n} nodes, u0 0.01, nu 0.01, FP64"
-    dev = torch.device("cuda:0")
     s = Solver(prob, device="cuda:0")
-    # warm-up first, so that a tuning run sees the flow the timed steps see (a
-    # power-law collision costs less where the fluid is still at rest); the
-    # autotuner restores the state it starts from
+    s.step(prerun)
     s.step(args.warmup)
-    torch.cuda.synchronize(dev)
-    tuned = None
-    choice = None
+    torch.cuda.synchronize()
     if args.variant >= 0 or args.tile_w or args.seg_h or args.prefetch or args.cost_scales:
         variant = args.variant if args.variant >= 0 else (1 if prob.pl_n != 1.0 else 2)
         s.set_kernel(variant, args.tile_w, args.seg_h, args.prefetch)
@@ -162,63 +172,186 @@ def main():
         if args.cost_scales:
             cx, cy = (float(t) for t in args.cost_scales.split(","))
             s.set_partition_costs(cx, cy)
-        if variant in (1, 2) and args.seg_h <= 0:
-            choice = (variant, 64 if variant == 2 else (args.tile_w or 64), args.prefetch or 2, cx, cy)
-    elif not args.no_autotune:
-        choice, cached = s.tuned(args.tuning, steps=40, retune=args.retune)
-        variant = int(choice[0])
-        tuned = {"variant": variant, "tile_w": choice[1], "prefetch": choice[2], "x_wall_cost_scale": choice[3],
-                 "y_wall_cost_scale": choice[4], "from_cache": cached}
+        tw = 64 if variant == 2 else (args.tile_w or 64)
+        choice = (variant, tw, args.prefetch or 2, cx, cy) if variant in (1, 2) and args.seg_h <= 0 else None
+        tuned = None
     else:
-        variant = 1 if prob.pl_n != 1.0 else 2
-    rounds = -args.seg_h if args.seg_h < 0 else 1
-    partition = (f"seg_h={args.seg_h}" if args.seg_h > 0 else
-                 f"balanced segment table, {rounds} round{'s' if rounds > 1 else ''} of workgroups")
-    tile_w = int(choice[1]) if choice else (args.tile_w or 64)
-    kname = {0: "three-pass (k_bar_plus, k_mid, k_hat_new)",
-             1: "k_fused (one wave per strip)" if tile_w == 64 else f"k_fused ({tile_w}-lane strips, one wave per 64)",
-             2: "k_fused2 (one wave per velocity component)"}[variant]
-    stream = s.stream
-
+        choice, cached = s.tuned(args.tuning, steps=40, retune=args.retune)
+        tuned = {"variant": int(choice[0]), "tile_w": int(choice[1]), "prefetch": int(choice[2]),
+                 "x_wall_cost_scale": choice[3], "y_wall_cost_scale": choice[4], "from_cache": cached}
+    state = s.save().cpu().numpy() if want_state else None
     s.step(5)   # first launches of the chosen kernel outside the timing
-    torch.cuda.synchronize(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    s.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize(dev)
+    ms = time_regions(s.step, s.stream, args.steps)
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
     diag, status = s.diagnostics()
-    if status != 0:
-        log(f"warning: diagnostics status {status}: {diag}")
-
+    if diverged(diag, status):
+        s.close()
+        fail_diverged(label, diag, status)
     if args.copy_calib > 0:
         for _ in range(args.copy_calib):
             s.save()
-        torch.cuda.synchronize(dev)
+        torch.cuda.synchronize()
+    med = statistics.median(ms)
+    out = {"label": label, "ms_per_step": med, "region_ms_per_step": [round(x, 6) for x in ms],
+           "mlups": prob.nodes / (med / 1e3) / 1e6, "choice": choice, "tuned": tuned, "wall_s": wall,
+           "diagnostics": diag_summary(diag, status), "state": state, "nodes": prob.nodes}
+    s.close()
+    return out
 
-    nodes = prob.nodes
-    sec = gpu_ms / 1e3
-    mlups = nodes * args.steps / sec / 1e6
-    # one step-kernel launch per step on the context's stream, plus one wall-rule
-    # launch per mdf_step call (a few microseconds once per timed region)
-    launch_s = sec / args.steps
-    achieved = BYTES_PER_NODE * nodes / launch_s / 1e9
-    # counter summaries are named by workload; the n = 3/2 power law has its own
-    stem = "powerlaw-n1.5-" if args.workload == "powerlaw" and args.pl_n != 0.5 else args.workload
-    traffic = measured_traffic(stem, args.n, choice)
+
+def cpu_baseline(probs_states, serial_steps, omp_steps):
+    """The oracle as it stands on the same workload: `serial_steps` steps of the
+    first problem on one thread, then `omp_steps` steps of every problem on
+    the OpenMP build of the same source over all host cores, each from the
+    GPU's state before the timed region."""
+    from oracle.orc import Oracle
+    cores = os.cpu_count() or 1
+    p0, f0 = probs_states[0]
+    o = Oracle(p0)
+    o.set_f(f0)
+    t0 = time.perf_counter()
+    o.step(serial_steps)
+    t_serial = time.perf_counter() - t0
+    serial = p0.nodes * serial_steps / t_serial / 1e6
+    del o
+    nodes, t_omp, threads = 0, 0.0, 1
+    for p, f in probs_states:
+        o = Oracle(p, threads=cores)
+        threads = o.threads
+        o.set_f(f)
+        t0 = time.perf_counter()
+        o.step(omp_steps)
+        t_omp += time.perf_counter() - t0
+        nodes += p.nodes * omp_steps
+        del o
+    return {"value": round(nodes / t_omp / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": cores,
+            "single_thread": {"value": round(serial, 4), "unit": "MLUPS", "cores": 1, "seconds": round(t_serial, 2)},
+            "sample": (f"{omp_steps} step(s) of each of the {len(probs_states)} timed runs on the OpenMP build "
+                       f"({threads} threads, {t_omp:.1f} s) and {serial_steps} step(s) of the first on the "
+                       f"sequential build ({t_serial:.1f} s), both from the GPU's state before the timed steps; "
+                       f"C oracle, -O2 -ffp-contract=off")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000, help="timed steps (per power-law index)")
+    ap.add_argument("--warmup", type=int, default=200, help="untimed steps before the timed ones")
+    ap.add_argument("--prerun", type=int, default=1000,
+                    help="steps from rest that prepare the input state of the power-law and cavity workloads")
+    ap.add_argument("--workload", choices=["powerlaw", "cavity", "taylor-green", "batch"], default="powerlaw",
+                    help="powerlaw: the benchmarked stretched power-law cavity (both indices unless --pl-n); "
+                         "cavity: lid-driven cavity Re 1000; taylor-green: periodic decaying vortex; "
+                         "batch: 256 periodic decaying-vortex instances of sizes 64..512 advanced together")
+    ap.add_argument("--n", type=int, default=0, help="nodes per side (default 2048; 1024 for the cavity)")
+    ap.add_argument("--pl-n", default="0.5,1.5", help="power-law indices of the powerlaw workload")
+    ap.add_argument("--tile-w", type=int, default=0)
+    ap.add_argument("--seg-h", type=int, default=0,
+                    help="rows per segment; -r: the balanced plan over r rounds of workgroups (0: library default)")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="step kernel: 0 three-pass, 1 fused one wave per strip, 2 fused one wave per "
+                         "velocity component (-1: the tuning cache's choice)")
+    ap.add_argument("--cpu-serial-steps", type=int, default=1, help="oracle steps on one thread (0 = skip baseline)")
+    ap.add_argument("--cpu-omp-steps", type=int, default=2, help="oracle steps per run on all cores")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary lines (1024^2 cavity, 256-instance batch)")
+    ap.add_argument("--tuning", default=TUNING,
+                    help="tuning cache: a kernel choice stored for this workload and device is used as is; "
+                         "otherwise the autotuner runs and its choice is stored")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner even if the cache holds a choice")
+    ap.add_argument("--prefetch", type=int, default=0, help="rows prefetched by the fused kernel (2 or 3)")
+    ap.add_argument("--cost-scales", default="",
+                    help="x,y scalings of the wall-row costs in the balanced partition (instead of the cache)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="after timing, run this many plain state copies (mdf_save) and streaming copies "
+                         "(mdf_stream_copy) as known-size references for HBM byte counters")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "the MDF-FDLBM step runs on exactly one GPU here; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    if args.steps < 1:
+        print(json.dumps({"error": "--steps must be >= 1"}), flush=True)
+        sys.exit(2)
+
+    import torch  # noqa: F401
+
+    from paper_2306_08216_amd import problems as P
+
+    if args.workload == "batch":
+        line = bench_batch(args)
+        if line.get("error"):
+            print(json.dumps(line), flush=True)
+            sys.exit(3)
+        print(json.dumps(line), flush=True)
+        return
+
+    runs, probs = [], []
+    if args.workload == "powerlaw":
+        n = args.n or 2048
+        indices = [float(t) for t in args.pl_n.split(",")]
+        for pl in indices:
+            prob = P.powerlaw_cavity(n, pl_n=pl)
+            log(f"power-law cavity n={pl:g} {n}^2: pre-run {args.prerun}, warm-up {args.warmup}, {args.steps} timed")
+            runs.append(run_solver(prob, args, f"n={pl:g}", args.prerun, want_state=args.cpu_serial_steps > 0))
+            probs.append(prob)
+        wl = (f"power-law lid-driven cavity, index n in {{{', '.join(f'{p:g}' for p in indices)}}}, "
+              f"tanh-stretched {n}x{n} grid (beta 1.5 both axes), Re_PL 100, lid 0.1, viscosity clamp "
+              f"[1e-2, 1e2] nu_ref, state pre-run {args.prerun} steps from rest, FP64")
+        stem = {0.5: "powerlaw", 1.5: "powerlaw-n1.5-"}
+    else:
+        n = args.n or 1024
+        if args.workload == "cavity":
+            prob = P.cavity(n, re=1000.0, lid=0.1)
+            wl = f"lid-driven cavity Re 1000, {n}x{n} nodes, lid 0.1, state pre-run {args.prerun} steps from rest, FP64"
+            prerun = args.prerun
+        else:
+            prob = P.taylor_green(n, u0=0.01, nu=0.01)
+            wl = f"periodic Taylor-Green vortex, {n}x{n} nodes, u0 0.01, nu 0.01, FP64"
+            prerun = 0
+        runs.append(run_solver(prob, args, args.workload, prerun, want_state=args.cpu_serial_steps > 0))
+        probs.append(prob)
+        stem = {1.0: args.workload}
+
+    nodes = sum(r["nodes"] for r in runs)
+    ms_per_step = sum(r["ms_per_step"] for r in runs)     # one step of every run
+    mlups = nodes / (ms_per_step / 1e3) / 1e6
+    achieved = BYTES_PER_NODE * nodes / (ms_per_step / 1e3) / 1e9
+    per_run = {}
+    for r, prob in zip(runs, probs):
+        key = stem.get(prob.pl_n, args.workload)
+        traffic = measured_traffic(key, n, r["choice"])
+        per_run[r["label"]] = {
+            "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "region_ms_per_step": r["region_ms_per_step"],
+            "achieved_GBs": round(BYTES_PER_NODE * r["nodes"] / (r["ms_per_step"] / 1e3) / 1e9, 1),
+            "frac": round(BYTES_PER_NODE * r["nodes"] / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel_choice": r["tuned"] or r["choice"], "diagnostics": r["diagnostics"],
+            "wall_s": round(r["wall_s"], 4)}
+
+    copy = copy_ceiling(int(BYTES_PER_NODE / 2 * runs[0]["nodes"]))
+    if args.copy_calib > 0:
+        import torch as _t
+        from paper_2306_08216_amd import _lib as L
+        nb = int(BYTES_PER_NODE / 2 * runs[0]["nodes"])
+        a = _t.ones(nb // 8, dtype=_t.float64, device="cuda:0")
+        b = _t.empty_like(a)
+        for _ in range(args.copy_calib):
+            L.mdf_stream_copy(a.data_ptr(), b.data_ptr(), nb, _t.cuda.current_stream().cuda_stream)
+        _t.cuda.synchronize()
+        del a, b
 
     cpu = None
-    if args.cpu_steps > 0:
-        v, el = cpu_baseline(prob, args.cpu_steps)
-        cpu = {"value": round(v, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_steps} steps of the same {args.n}x{args.n} {args.workload} after 1 untimed step "
-                         f"({el:.1f} s, single-threaded C oracle, -O2 -ffp-contract=off)"}
+    if args.cpu_serial_steps > 0:
+        cpu = cpu_baseline([(p, r["state"]) for p, r in zip(probs, runs)], args.cpu_serial_steps,
+                           max(1, args.cpu_omp_steps))
 
+    traffic_vals = [v["traffic"] for v in per_run.values()]
+    traffic = sum(traffic_vals) / len(traffic_vals) if all(t is not None for t in traffic_vals) else None
+    first = runs[0]
+    kname = "k_fused" if (first["tuned"] or {}).get("variant", (first["choice"] or [1])[0]) == 1 else "k_fused2"
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -226,26 +359,51 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup + 5,
-        "ms_per_step": gpu_ms / args.steps,
+        "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl,
-                   "kernel": kname,
-                   "partition": partition,
-                   "autotuned": tuned,
-                   "wall_s": round(wall, 4)},
+                   "nodes_per_step": nodes,
+                   "timing": f"{args.steps} steps per run as {REGIONS} event-timed regions; median region",
+                   "runs": per_run},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes},
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * runs[0]["nodes"],
+                     "kernel": kname,
+                     "copy_ceiling": copy,
+                     "frac_of_copy": round(achieved / copy["GB/s"], 4)},
         "cpu_baseline": cpu,
     }
+    if args.workload == "powerlaw" and not args.no_secondary:
+        out["secondary"] = secondary_lines(args)
     print(json.dumps(out), flush=True)
-    s.close()
+
+
+def secondary_lines(args):
+    """Context lines: the 1024^2 cavity (cache-resident pair) and the batch."""
+    from paper_2306_08216_amd import problems as P
+
+    class A:
+        pass
+    a = A()
+    for k, v in vars(args).items():
+        setattr(a, k, v)
+    a.steps, a.warmup, a.variant, a.tile_w, a.seg_h, a.prefetch, a.cost_scales, a.copy_calib = \
+        min(args.steps, 2000), 200, -1, 0, 0, 0, "", 0
+    prob = P.cavity(1024, re=1000.0, lid=0.1)
+    r = run_solver(prob, a, "cavity1024", 1000)
+    cav = {"workload": "lid-driven cavity Re 1000, 1024x1024 (state pair fits the 256 MB Infinity Cache: "
+                       "effective bandwidth)", "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"],
+           "frac_effective": round(BYTES_PER_NODE * prob.nodes / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "kernel_choice": r["tuned"], "steps": a.steps}
+    a.steps = min(args.steps, 500)
+    bat = bench_batch(a)
+    return {"cavity1024": cav, "batch256": bat}
 
 
 def bench_batch(args):
@@ -263,43 +421,39 @@ def bench_batch(args):
     b = BatchSolver(probs)
     choice, cached = b.autotune(args.tuning, steps=10, retune=args.retune)
     nodes = b.nodes
-    steps = min(args.steps, 500)
+    per_region = max(1, args.steps // REGIONS)
     b.step(min(args.warmup, 50))
+    b.step_graph(per_region)     # capture both starting buffers outside the timing
+    b.step_graph(per_region)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(b.stream)
-    b.step_graph(steps)
-    ev1.record(b.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
+    ms = time_regions(b.step_graph, b.stream, REGIONS * per_region)
+    med = statistics.median(ms)
+    workgroups = b.workgroups
+    worst = None
+    for i in range(b.count):
+        d, st = b.diagnostics(i)
+        if diverged(d, st):
+            worst = (i, d, st)
+            break
     if args.copy_calib > 0:
-        # known-size copies (k_pack, 80 B read + 80 B written per node) of the
-        # largest instances, the reference for the byte counters
         big = sorted(range(b.count), key=lambda i: -probs[i].nodes)[:args.copy_calib]
         for i in big:
             b.save(i)
         torch.cuda.synchronize()
-    mlups = nodes * steps / (ms / 1e3) / 1e6
-    achieved = BYTES_PER_NODE * nodes / (ms / 1e3 / steps) / 1e9
-    out = {
-        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
-        "warmup": min(args.warmup, 50), "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batch of 256 periodic decaying vortices, sizes 64..512, {nodes} nodes, FP64",
-                   "kernel": {1: "k_fused_batch", 2: "k_fused2_batch"}[choice[0]],
-                   "autotuned": {"variant": choice[0], "tile_w": choice[3], "prefetch": choice[1], "rounds": choice[2],
-                                 "from_cache": cached},
-                   "workgroups": b.workgroups, "graph": True, "wall_s": round(wall, 4)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_batch_traffic(choice),
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes},
-        "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
     b.close()
+    if worst is not None:
+        return {"error": f"instance {worst[0]} holds a non-finite value", "diagnostics": diag_summary(worst[1], worst[2])}
+    achieved = BYTES_PER_NODE * nodes / (med / 1e3) / 1e9
+    return {"workload": f"batch of 256 periodic decaying vortices, sizes 64..512, {nodes} nodes, FP64",
+            "metric": METRIC, "value": round(nodes / (med / 1e3) / 1e6, 2), "unit": "MLUPS",
+            "ms_per_step": med, "steps": REGIONS * per_region, "graph": True,
+            "kernel": {1: "k_fused_batch", 2: "k_fused2_batch"}[choice[0]],
+            "kernel_choice": {"variant": choice[0], "tile_w": choice[3], "prefetch": choice[1], "rounds": choice[2],
+                              "from_cache": cached},
+            "workgroups": workgroups,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_batch_traffic(choice),
+                         "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes}}
 
 
 if __name__ == "__main__":

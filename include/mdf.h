@@ -66,10 +66,14 @@ typedef struct {
     const double* inv_dx_x;  /* HOST, nx values: 1/(X'(xi_i) dxi) of a mapped x axis, or NULL (uniform) */
     const double* inv_dx_y;  /* HOST, ny values, same for y, or NULL                                */
     double  dx_min;          /* smallest node spacing; required when either metric array is given */
+    const double* force_x;   /* HOST, ny*nx values (x fastest) added to fx at each node: a steady body
+                                force field F(x) (eq. 2.2.6, Secs. 4.1-4.2), or NULL (none)          */
+    const double* force_y;   /* HOST, ny*nx values added to fy, or NULL                            */
 } mdf_params;
 
 /* Bytes of device workspace a context for these parameters needs, or 0 if the
- * parameters are invalid.  Depends only on nx and ny. */
+ * parameters are invalid.  Depends only on nx, ny and whether a force field
+ * (force_x or force_y) is given. */
 size_t mdf_workspace_size(const mdf_params* p);
 
 /* Create a context and initialise the state f_hat = f^eq(u0, v0, p0) of
@@ -85,7 +89,8 @@ size_t mdf_workspace_size(const mdf_params* p);
  * cfl <= 0, c <= 0, eta outside [0,1], an axis has fewer than 5 or more than
  * 32768 nodes, pl_n is
  * not 1, 0.5 or 1.5, the power-law clamp is empty, metrics come without dx_min,
- * or the workspace is too small or misaligned. */
+ * a metric or force value is not finite, or the workspace is too small or
+ * misaligned.  The metric and force arrays are copied; p may be freed after. */
 mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0,
                     void* workspace, size_t ws_bytes, void* hip_stream, mdf_ctx** out);
 
@@ -131,7 +136,8 @@ mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, cons
  * tile_w (columns per strip incl. the 8-column halo, one wave per 64; 64,
  * 128 or 256, variant 1 only), seg_h and prefetch (rows loaded ahead, 2 or 3;
  * 2 with 256 lanes) apply to the fused
- * variants; 0 keeps the current value.  seg_h > 0 cuts every strip into
+ * variants; 0 keeps the current value.  With a force field only variants 0
+ * and 1 exist, variant 1 with tile_w 64 and prefetch 2 (the default then).  seg_h > 0 cuts every strip into
  * segments of seg_h rows; seg_h = -r (r = 1..4; -1 is the default) selects
  * the balanced partition over r rounds of waves on the device (one wave per
  * SIMD per round; a 128-lane strip takes two), with fewer rows in the
@@ -147,7 +153,8 @@ mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t
 mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_wall_scale);
 
 /* Autotuner for this context: times every fused kernel (variant 1 with
- * tile_w 64, 128 and 256, and variant 2 for a Newtonian fluid), prefetch
+ * tile_w 64, 128 and 256, and variant 2 for a Newtonian fluid; only variant 1
+ * with tile_w 64 and prefetch 2 under a force field), prefetch
  * depth (2, 3; 2 with 256 lanes) and eight scalings (0.3..3.5) of the
  * wall-row cost factors of the one-round balanced partition over `steps`
  * steps of the run itself, times the three fastest again over 4 x `steps`
@@ -275,12 +282,27 @@ mdf_status mdf_batch_autotune(mdf_batch* b, int32_t steps, int32_t* choice);
  * mdf_save); asynchronous on the batch's stream. */
 mdf_status mdf_batch_moments(mdf_batch* b, int32_t i, double* u, double* v, double* p);
 mdf_status mdf_batch_save(mdf_batch* b, int32_t i, double* f);
+/* Instance i's local quantities of Sec. 2.4 (eqs. 2.4.1-2.4.5), planes and
+ * mask exactly as mdf_derived (DEVICE out, ny_i*nx_i doubles per selected
+ * plane); asynchronous on the batch's stream. */
+mdf_status mdf_batch_derived(mdf_batch* b, int32_t i, double* out, uint32_t mask);
+/* Instance i's diagnostics into HOST out[8], as mdf_diagnostics; synchronises
+ * the batch's stream; MDF_EUNSTABLE (out filled) on a non-finite value. */
+mdf_status mdf_batch_diagnostics(mdf_batch* b, int32_t i, double out[8]);
 
 double      mdf_batch_dt(const mdf_batch* b, int32_t i);   /* instance time step, 0 if invalid */
 int64_t     mdf_batch_steps(const mdf_batch* b);          /* steps since mdf_batch_init       */
 int32_t     mdf_batch_workgroups(const mdf_batch* b);     /* workgroups of one step launch    */
 const char* mdf_batch_last_error(const mdf_batch* b);     /* never NULL                       */
 void        mdf_batch_destroy(mdf_batch* b);               /* synchronises; NULL is a no-op    */
+
+/* ---------------------------------------------------------------------------
+ * Measurement aid (not part of the method): a streaming copy of `bytes`
+ * bytes (a multiple of 16; both DEVICE pointers 16-byte aligned, regions not
+ * overlapping) with 16-byte loads and stores, asynchronous on hip_stream.  Its
+ * rate is the practical HBM ceiling the step's bandwidth is compared with, and
+ * its known traffic calibrates the hardware byte counters. */
+mdf_status mdf_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

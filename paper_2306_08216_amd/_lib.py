@@ -31,6 +31,7 @@ class mdf_params(C.Structure):
         ("fx", C.c_double), ("fy", C.c_double),
         ("inv_dx_x", _dp), ("inv_dx_y", _dp),
         ("dx_min", C.c_double),
+        ("force_x", _dp), ("force_y", _dp),
     ]
 
 
@@ -77,11 +78,14 @@ SIGNATURES = {
     "mdf_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "mdf_batch_moments": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mdf_batch_save": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "mdf_batch_derived": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint32]),
+    "mdf_batch_diagnostics": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "mdf_batch_dt": (C.c_double, [C.c_void_p, C.c_int32]),
     "mdf_batch_steps": (C.c_int64, [C.c_void_p]),
     "mdf_batch_workgroups": (C.c_int32, [C.c_void_p]),
     "mdf_batch_last_error": (C.c_char_p, [C.c_void_p]),
     "mdf_batch_destroy": (None, [C.c_void_p]),
+    "mdf_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
 }
 
 _lib = None
@@ -242,6 +246,22 @@ def mdf_batch_moments(b: int, i: int, u: int, v: int, p: int):
 
 def mdf_batch_save(b: int, i: int, f: int):
     return bcheck(lib().mdf_batch_save(b, int(i), f), b)
+
+
+def mdf_batch_derived(b: int, i: int, out: int, mask: int):
+    return bcheck(lib().mdf_batch_derived(b, int(i), out, int(mask)), b)
+
+
+def mdf_batch_diagnostics(b: int, i: int, out8):
+    """Returns the status (MDF_OK or MDF_EUNSTABLE); out8 is filled either way."""
+    st = lib().mdf_batch_diagnostics(b, int(i), out8)
+    if st not in (MDF_OK, MDF_EUNSTABLE):
+        bcheck(st, b)
+    return st
+
+
+def mdf_stream_copy(src: int, dst: int, nbytes: int, stream: int):
+    return check(lib().mdf_stream_copy(src, dst, int(nbytes), stream))
 
 
 def mdf_batch_dt(b: int, i: int) -> float:

@@ -114,6 +114,19 @@ class BatchSolver:
         L.mdf_batch_moments(self.b, i, u.data_ptr(), v.data_ptr(), pr.data_ptr())
         return u, v, pr
 
+    def derived(self, i: int, mask: int = (1 << 14) - 1) -> torch.Tensor:
+        """Instance i's local quantities of Sec. 2.4 (planes as Solver.derived)."""
+        p = self.probs[i]
+        out = torch.empty((bin(mask).count("1"), p.ny, p.nx), dtype=torch.float64, device=self.device)
+        L.mdf_batch_derived(self.b, i, out.data_ptr(), mask)
+        return out
+
+    def diagnostics(self, i: int):
+        """Instance i's eight diagnostics (as Solver.diagnostics) and the status."""
+        buf = (C.c_double * 8)()
+        status = L.mdf_batch_diagnostics(self.b, i, buf)
+        return np.array(buf[:]), status
+
     def save(self, i: int) -> torch.Tensor:
         p = self.probs[i]
         f = torch.empty((10, p.ny, p.nx), dtype=torch.float64, device=self.device)

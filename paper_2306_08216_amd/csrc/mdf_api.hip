@@ -64,14 +64,16 @@ mdf_status hip_check(mdf_ctx* c, hipError_t e, const char* what)
 
 struct Layout {
     size_t pitch;                 // nodes per row
-    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, off_seg, total;  // bytes
+    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, off_seg, off_ff, total;  // bytes
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 constexpr int kSegCap = 4096;   // entries of the segment table (one per workgroup)
 
-Layout layout_for(int nx, int ny)
+bool has_force_field(const mdf_params* p) { return p->force_x != nullptr || p->force_y != nullptr; }
+
+Layout layout_for(int nx, int ny, bool force_field)
 {
     Layout L;
     // rows of 80 bytes per node (x-part block, then y-part block); 16-node multiples keep
@@ -88,6 +90,8 @@ Layout layout_for(int nx, int ny)
     L.off_dp = o;   o += align256(8 * 1024 * sizeof(double));
     L.off_do = o;   o += align256(8 * sizeof(double));
     L.off_seg = o;  o += align256(kSegCap * sizeof(int4));
+    // force field: (F_x, F_y) per node in rows of pitch nodes
+    L.off_ff = o;   o += force_field ? align256(2 * L.pitch * (size_t)ny * sizeof(double)) : 0;
     L.total = o;
     return L;
 }
@@ -155,6 +159,10 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.lam_h = 0.5 * K.h * p.c;
     K.lam_dt = 0.5 * K.dt * p.c;
     K.uniform = (p.inv_dx_x == nullptr && p.inv_dx_y == nullptr) ? 1 : 0;
+    K.ginv[0] = 1.0 / hx;
+    K.ginv[1] = 1.0 / hy;
+    K.gx = nullptr;
+    K.gy = nullptr;
     {
         const double g[2] = {1.0 / hx, 1.0 / hy};
         for (int ax = 0; ax < 2; ++ax) {
@@ -168,6 +176,9 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.hwf[1] = K.h * K.w * p.fy;
     K.dwf[0] = K.dt * K.w * p.fx;
     K.dwf[1] = K.dt * K.w * p.fy;
+    K.hw = K.h * K.w;
+    K.dw = K.dt * K.w;
+    K.ff = nullptr;
     return K;
 }
 
@@ -318,6 +329,8 @@ struct mdf_batch {
     size_t ws_bytes = 0;
     double* f[2] = {nullptr, nullptr};
     double* backup = nullptr;       // copy of the state while the autotuner runs
+    double* diag_part = nullptr;    // diagnostics partials and result
+    double* diag_out = nullptr;
     size_t state_doubles = 0;       // doubles of one state buffer (all instances)
     mdf::BatchInst* d_insts = nullptr;
     int4* d_table = nullptr;
@@ -335,7 +348,7 @@ struct mdf_batch {
 namespace {
 
 struct BatchLayout {
-    size_t off_insts, off_table, off_f0, off_f1, off_backup, total;
+    size_t off_insts, off_table, off_f0, off_f1, off_backup, off_dp, off_do, total;
     size_t state_doubles;
     int table_cap;
     std::vector<long long> offs;   // per instance, doubles
@@ -351,6 +364,7 @@ const char* validate_batch(const mdf_params* ps, int count)
         if (ps[i].bc_x != MDF_BC_PERIODIC || ps[i].bc_y != MDF_BC_PERIODIC)
             return "batched instances must be periodic on both axes";
         if (ps[i].inv_dx_x || ps[i].inv_dx_y) return "batched instances must use uniform grids";
+        if (has_force_field(&ps[i])) return "batched instances take a uniform force only";
         if (ps[i].pl_n != ps[0].pl_n) return "batched instances must share the fluid model (pl_n)";
     }
     return nullptr;
@@ -378,6 +392,8 @@ BatchLayout batch_layout(const mdf_params* ps, int count)
     B.off_f0 = t;     t += o;
     B.off_f1 = t;     t += o;
     B.off_backup = t; t += o;
+    B.off_dp = t;     t += align256(8 * 1024 * sizeof(double));   // diagnostics partials
+    B.off_do = t;     t += align256(8 * sizeof(double));
     B.total = t;
     return B;
 }
@@ -440,7 +456,7 @@ extern "C" {
 size_t mdf_workspace_size(const mdf_params* p)
 {
     if (validate(p)) return 0;
-    return layout_for(p->nx, p->ny).total;
+    return layout_for(p->nx, p->ny, has_force_field(p)).total;
 }
 
 mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0, void* workspace,
@@ -450,7 +466,7 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     *out = nullptr;
     if (const char* why = validate(p)) return fail(nullptr, MDF_EINVAL, "%s", why);
     if (!u0 || !v0 || !p0) return fail(nullptr, MDF_EINVAL, "initial fields must be non-NULL device pointers");
-    const Layout L = layout_for(p->nx, p->ny);
+    const Layout L = layout_for(p->nx, p->ny, has_force_field(p));
     if (!workspace || ws_bytes < L.total)
         return fail(nullptr, MDF_EINVAL, "workspace too small: need %zu bytes, got %zu", L.total, ws_bytes);
     if (((uintptr_t)workspace & 255u) != 0) return fail(nullptr, MDF_EINVAL, "workspace must be 256-byte aligned");
@@ -460,6 +476,8 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     c->p = *p;
     c->p.inv_dx_x = nullptr;
     c->p.inv_dx_y = nullptr;
+    c->p.force_x = nullptr;
+    c->p.force_y = nullptr;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char*)workspace;
     c->ws_bytes = ws_bytes;
@@ -483,8 +501,9 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     c->shape = default_shape();
     // one wave per velocity component fits two waves per SIMD for a Newtonian
     // fluid; the power-law viscosity solve needs more registers than that
-    // allows, and there one wave per strip is faster
-    c->variant = p->pl_n == 1.0 ? 2 : 1;
+    // allows, and there one wave per strip is faster.  A force field has
+    // kernels of the second kind only.
+    c->variant = (p->pl_n == 1.0 && !has_force_field(p)) ? 2 : 1;
 
     // derivative scales 1/(X' dxi) per node (uniform: 1/dx)
     std::string hbuf;
@@ -514,6 +533,36 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
             delete c;
             return s;
         }
+    }
+    // force field: the uniform force plus the given field, (F_x, F_y) per node
+    if (has_force_field(p)) {
+        const size_t pitch = L.pitch, n2 = 2 * pitch * (size_t)p->ny;
+        std::vector<double> ffh;
+        try {
+            ffh.assign(n2, 0.0);
+        } catch (...) {
+            delete c;
+            return fail(nullptr, MDF_EDEVICE, "out of host memory");
+        }
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                const size_t i = (size_t)y * p->nx + x, o = ((size_t)y * pitch + x) * 2;
+                ffh[o] = p->fx + (p->force_x ? p->force_x[i] : 0.0);
+                ffh[o + 1] = p->fy + (p->force_y ? p->force_y[i] : 0.0);
+                if (!std::isfinite(ffh[o]) || !std::isfinite(ffh[o + 1])) {
+                    delete c;
+                    return fail(nullptr, MDF_EINVAL, "force field values must be finite");
+                }
+            }
+        double* dff = (double*)(c->ws + L.off_ff);
+        hipError_t e = hipMemcpyAsync(dff, ffh.data(), sizeof(double) * n2, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            mdf_status s = hip_check(nullptr, e, "force field upload");
+            delete c;
+            return s;
+        }
+        c->K.ff = dff;
     }
     {
         const mdf_status s = prepare_shape(c);
@@ -614,6 +663,7 @@ mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t s
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
     if (variant < 0 || variant > 2) return fail(c, MDF_EINVAL, "variant must be 0, 1 or 2");
+    if (variant == 2 && c->K.ff) return fail(c, MDF_EINVAL, "a force field runs on variant 0 or 1 only");
     if (seg_h < -4) return fail(c, MDF_EINVAL, "seg_h below 0 selects 1 to 4 rounds of the balanced table");
     mdf::FusedShape sh = c->shape;
     int rounds = c->rounds;
@@ -624,8 +674,10 @@ mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t s
         rounds = -seg_h;
     }
     if (prefetch) sh.prefetch = prefetch;
-    if (!mdf::fused_shape_ok(c->K, sh))
-        return fail(c, MDF_EINVAL, "tile_w must be 64 or 128 with prefetch 2 or 3, or 256 with prefetch 2");
+    if (variant != 0 && !mdf::fused_shape_ok(c->K, sh))
+        return fail(c, MDF_EINVAL,
+                    c->K.ff ? "a force field takes tile_w 64 and prefetch 2"
+                            : "tile_w must be 64 or 128 with prefetch 2 or 3, or 256 with prefetch 2");
     const int old_variant = c->variant, old_rounds = c->rounds;
     const mdf::FusedShape old_shape = c->shape;
     c->variant = variant;
@@ -709,10 +761,12 @@ mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
                                  {1.7, 1.3}, {2.2, 1.6}, {2.8, 2.0}, {3.5, 2.4}};
     std::vector<Cand> cands;
     const int kernels[4][3] = {{1, 64, 3}, {1, 128, 3}, {1, 256, 2}, {2, 64, 3}};
+    const bool field = c->K.ff != nullptr;
     for (int kv = 0; kv < 4; ++kv) {
         const int var = kernels[kv][0], tw = kernels[kv][1];
-        if (var == 2 && power) continue;
-        for (int pf = 2; pf <= kernels[kv][2]; ++pf)
+        if (var == 2 && (power || field)) continue;
+        if (field && tw != 64) continue;
+        for (int pf = 2; pf <= (field ? 2 : kernels[kv][2]); ++pf)
             for (int sc = 0; sc < 8; ++sc) cands.push_back(Cand{var, tw, pf, scales[sc][0], scales[sc][1], 1e30f});
     }
     auto apply = [&](const Cand& k) {
@@ -901,6 +955,8 @@ mdf_status mdf_batch_init(const mdf_params* ps, int32_t count, const double* con
     b->f[0] = (double*)(b->ws + B.off_f0);
     b->f[1] = (double*)(b->ws + B.off_f1);
     b->backup = (double*)(b->ws + B.off_backup);
+    b->diag_part = (double*)(b->ws + B.off_dp);
+    b->diag_out = (double*)(b->ws + B.off_do);
     b->state_doubles = B.state_doubles;
     b->powerlaw = ps[0].pl_n != 1.0;
     b->variant = b->powerlaw ? 1 : 2;
@@ -1107,6 +1163,30 @@ mdf_status mdf_batch_save(mdf_batch* b, int32_t i, double* f)
     return bhip(b, mdf::launch_pack(I.K, b->f[b->cur] + I.off, f, b->stream), "batch save launch");
 }
 
+mdf_status mdf_batch_derived(mdf_batch* b, int32_t i, double* out, uint32_t mask)
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (i < 0 || i >= b->count) return bfail(b, MDF_EINVAL, "instance index out of range");
+    if (!out) return bfail(b, MDF_EINVAL, "out is NULL");
+    if (mask == 0 || mask >= (1u << 14)) return bfail(b, MDF_EINVAL, "mask must be in [1, 2^14)");
+    const mdf::BatchInst& I = b->insts[i];
+    return bhip(b, mdf::launch_derived(I.K, b->f[b->cur] + I.off, out, mask, b->stream), "batch derived launch");
+}
+
+mdf_status mdf_batch_diagnostics(mdf_batch* b, int32_t i, double out[8])
+{
+    if (!b) return fail(nullptr, MDF_EINVAL, "batch is NULL");
+    if (i < 0 || i >= b->count) return bfail(b, MDF_EINVAL, "instance index out of range");
+    if (!out) return bfail(b, MDF_EINVAL, "out is NULL");
+    const mdf::BatchInst& I = b->insts[i];
+    hipError_t e = mdf::launch_diagnostics(I.K, b->f[b->cur] + I.off, b->diag_part, b->diag_out, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, b->diag_out, 8 * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "batch diagnostics");
+    if (out[6] != 0.0) return bfail(b, MDF_EUNSTABLE, "instance state holds non-finite values");
+    return MDF_OK;
+}
+
 double mdf_batch_dt(const mdf_batch* b, int32_t i)
 {
     if (!b || i < 0 || i >= b->count) return 0.0;
@@ -1133,6 +1213,17 @@ void mdf_batch_destroy(mdf_batch* b)
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->gstream) (void)hipStreamDestroy(b->gstream);
     delete b;
+}
+
+mdf_status mdf_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream)
+{
+    if (!src || !dst) return fail(nullptr, MDF_EINVAL, "src and dst must be non-NULL");
+    if ((bytes & 15) != 0 || ((uintptr_t)src & 15) != 0 || ((uintptr_t)dst & 15) != 0)
+        return fail(nullptr, MDF_EINVAL, "bytes and both pointers must be multiples of 16");
+    const uintptr_t a = (uintptr_t)src, d = (uintptr_t)dst;
+    if (bytes > 0 && a < d + bytes && d < a + bytes) return fail(nullptr, MDF_EINVAL, "regions overlap");
+    if (bytes == 0) return MDF_OK;
+    return hip_check(nullptr, mdf::launch_stream_copy(src, dst, bytes, (hipStream_t)hip_stream), "stream copy");
 }
 
 }  // extern "C"

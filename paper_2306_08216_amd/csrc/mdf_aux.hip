@@ -64,12 +64,12 @@ __device__ __forceinline__ double transport_at(const StepConsts& K, const double
     const int j = q % 5;
     if (j == 0) return 0.0;
     if (j == 1 || j == 3) {
-        const double lg = lam * K.gx[x];
+        const double lg = lam * gx_at(K, x);
         const double pm1 = fetch(K, f, q, x - 1, y), p0 = fetch(K, f, q, x, y), p1 = fetch(K, f, q, x + 1, y);
         if (j == 1) return transport_pos(K, lg, fetch(K, f, q, x - 2, y), pm1, p0, p1);
         return transport_neg(K, lg, pm1, p0, p1, fetch(K, f, q, x + 2, y));
     }
-    const double lg = lam * K.gy[y];
+    const double lg = lam * gy_at(K, y);
     const double pm1 = fetch(K, f, q, x, y - 1), p0 = fetch(K, f, q, x, y), p1 = fetch(K, f, q, x, y + 1);
     if (j == 2) return transport_pos(K, lg, fetch(K, f, q, x, y - 2), pm1, p0, p1);
     return transport_neg(K, lg, pm1, p0, p1, fetch(K, f, q, x, y + 2));
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
         load10(K, f, x, y, fh);
         node_moments(fh, K.c, u, v, P);
         derived_node(K, fh, d);
-        const double dA = 1.0 / (K.gx[x] * K.gy[y]);
+        const double dA = 1.0 / (gx_at(K, x) * gy_at(K, y));
         acc[0] += u;
         acc[1] += v;
         acc[2] += 0.5 * (u * u + v * v) * dA;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
             node_moments(a, K.c, t0, vn, t2);
             load10(K, f, x, ym, b);
             node_moments(b, K.c, t0, vs, t2);
-            const double div = (ue - uw) * K.gx[x] * 0.5 + (vn - vs) * K.gy[y] * 0.5;
+            const double div = (ue - uw) * gx_at(K, x) * 0.5 + (vn - vs) * gy_at(K, y) * 0.5;
             acc[5] = fmax(acc[5], fabs(div));
         }
         int bad = 0;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void mid_at(const StepConsts& K, const double* fbp, i
     double fb[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k)
-        fb[k] = comp(K, fbp, x, y, k) - transport_at(K, fbp, k, x, y, K.lam_h) + K.hwf[k / 5];
+        fb[k] = comp(K, fbp, x, y, k) - transport_at(K, fbp, k, x, y, K.lam_h) + hwf_at(K, x, y, k / 5);
     collide3(K, fb, f);
 }
 
@@ -330,7 +330,7 @@ __device__ __forceinline__ void full_at(const StepConsts& K, const double* fh, c
     load10(K, fh, x, y, a);
     collide1_hat(K, a, fhp);
 #pragma unroll
-    for (int k = 0; k < 10; ++k) out[k] = fhp[k] - transport_at(K, fmid, k, x, y, K.lam_dt) + K.dwf[k / 5];
+    for (int k = 0; k < 10; ++k) out[k] = fhp[k] - transport_at(K, fmid, k, x, y, K.lam_dt) + dwf_at(K, x, y, k / 5);
 }
 
 __global__ void k_pass_c(StepConsts K, const double* __restrict__ fh, const double* __restrict__ fmid,
@@ -397,6 +397,35 @@ hipError_t launch_diagnostics(const StepConsts& K, const double* f, double* part
     const int nb = diag_blocks(K);
     hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(DIAG_BLOCK), 0, s, K, f, partials);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DIAG_BLOCK), 0, s, partials, nb, out8);
+    return hipGetLastError();
+}
+
+// Streaming copy: each thread moves four 16-byte units per pass, 256 units
+// apart so that a wave's loads cover 1 KiB contiguous each; the grid is sized
+// to keep every compute unit busy and loops over the rest.
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                     size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * 1024;
+    size_t i = (size_t)blockIdx.x * 1024 + threadIdx.x;
+    for (; i + 768 < n16; i += stride) {
+        const uint4 a = src[i], b = src[i + 256], c = src[i + 512], d = src[i + 768];
+        dst[i] = a;
+        dst[i + 256] = b;
+        dst[i + 512] = c;
+        dst[i + 768] = d;
+    }
+    for (int k = 0; k < 4; ++k)
+        if (i + 256 * k < n16) dst[i + 256 * k] = src[i + 256 * k];
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    size_t blocks = (n16 + 1023) / 1024;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
     return hipGetLastError();
 }
 

@@ -358,7 +358,9 @@ struct CnnLayout {
 
 size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
-CnnLayout cnn_layout(int B, int H, int W)
+// Workspace layout for batch B of H x W fields; without `training` only the
+// forward pass's buffers (no gradients, partials or loss).
+CnnLayout cnn_layout(int B, int H, int W, bool training = true)
 {
     CnnLayout L{};
     L.P = (size_t)B * H * W;
@@ -376,6 +378,14 @@ CnnLayout cnn_layout(int B, int H, int W)
         L.a[l] = take(L.P * 32 * 2);
     }
     L.z[4] = take(L.P * 2 * 4);
+    if (!training) {
+        for (int l = 0; l < 4; ++l) {
+            L.wf[l] = take(9 * 32 * 32 * 2);
+            L.wb[l] = take(9 * 32 * 32 * 2);
+        }
+        L.total = o;
+        return L;
+    }
     // gradient of the loss at each layer output z_l (l = 1..4), 32 channels wide
     for (int l = 1; l <= 4; ++l) {
         L.g32[l] = take(L.P * 32 * 4);
@@ -477,10 +487,11 @@ hipError_t launch_closure_apply(const StepConsts& K, double* f, const double* du
 
 size_t cnn_workspace_size(int B, int H, int W) { return cnn_layout(B, H, W).total; }
 
-hipError_t cnn_forward(char* ws, const float* params, int B, int H, int W, const double* uv, double in_scale,
-                       double out_scale, double* duv, hipStream_t s)
+namespace {
+
+hipError_t forward_at(const CnnLayout& L, char* ws, const float* params, int B, int H, int W, const double* uv,
+                      double in_scale, double out_scale, double* duv, hipStream_t s)
 {
-    const CnnLayout L = cnn_layout(B, H, W);
     hipError_t e = pack_all(L, ws, params, s);
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((L.P + 255) / 256);
@@ -502,6 +513,14 @@ hipError_t cnn_forward(char* ws, const float* params, int B, int H, int W, const
     hipLaunchKernelGGL(k_unpack_output, dim3(nb), dim3(256), 0, s, (const float*)(ws + L.z[4]), B, H, W, out_scale,
                        duv);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t cnn_forward(char* ws, const float* params, int B, int H, int W, const double* uv, double in_scale,
+                       double out_scale, double* duv, hipStream_t s)
+{
+    return forward_at(cnn_layout(B, H, W), ws, params, B, H, W, uv, in_scale, out_scale, duv, s);
 }
 
 hipError_t cnn_backward(char* ws, const float* params, int B, int H, int W, const double* duv_t, double out_scale,

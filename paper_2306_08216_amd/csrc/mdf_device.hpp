@@ -42,10 +42,16 @@ struct StepConsts {
     double theta1, theta3;   // c_s^2 dt/2 and c_s^2 dt/4
     // transport coefficients: tau * c / 2 for tau = h and tau = dt
     double lam_h, lam_dt;
-    // body force terms h w F_alpha and dt w F_alpha
+    // body force terms h w F_alpha and dt w F_alpha of a uniform force
     double hwf[2], dwf[2];
-    const double* gx;        // nx derivative scales 1/(X' dxi)
-    const double* gy;        // ny derivative scales
+    const double* gx;        // nx derivative scales 1/(X' dxi), or null on a uniform grid
+    const double* gy;        // ny derivative scales, or null
+    double ginv[2];          // 1/dx and 1/dy of the uniform spacing (used where gx, gy are null)
+    // steady force field (eq. 2.2.6 with F depending on x): (F_x, F_y) per node,
+    // rows of pitch nodes, uniform part included; null for a uniform force.
+    // Steps (2) and (4) then add hw F and dw F with hw = h w, dw = dt w.
+    const double* ff;
+    double hw, dw;
 };
 
 // State layout (row-split).  Row y occupies 80*pitch contiguous bytes: first
@@ -426,6 +432,23 @@ __device__ __forceinline__ double upd_neg(const Stencil& k, double base, double 
 }
 
 __device__ __forceinline__ double ghost(double p0, double p1, double p2) { return 3.0 * p0 - 3.0 * p1 + p2; }
+
+// derivative scale of column x and row y: the metric arrays where the run has
+// them, else the uniform 1/dx, 1/dy (batch instances carry no arrays)
+__device__ __forceinline__ double gx_at(const StepConsts& K, int x) { return K.gx ? K.gx[x] : K.ginv[0]; }
+__device__ __forceinline__ double gy_at(const StepConsts& K, int y) { return K.gy ? K.gy[y] : K.ginv[1]; }
+
+// h w F_alpha and dt w F_alpha at node (x, y) for alpha index a: the force
+// field when one is set, else the uniform force
+__device__ __forceinline__ double hwf_at(const StepConsts& K, int x, int y, int a)
+{
+    return K.ff ? K.hw * K.ff[((size_t)y * K.pitch + x) * 2 + a] : K.hwf[a];
+}
+
+__device__ __forceinline__ double dwf_at(const StepConsts& K, int x, int y, int a)
+{
+    return K.ff ? K.dw * K.ff[((size_t)y * K.pitch + x) * 2 + a] : K.dwf[a];
+}
 
 __device__ __forceinline__ bool is_wall(const StepConsts& K, int x, int y)
 {

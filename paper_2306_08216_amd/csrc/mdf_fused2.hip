@@ -524,6 +524,7 @@ hipError_t launch_fused2_batch(const BatchInst* insts, const int4* table, int nw
 
 hipError_t launch_fused2(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s)
 {
+    if (K.ff) return hipErrorInvalidValue;   // no force-field path in this kernel
     Grid2 G;
     const int wout = TW2 - 8;
     G.nstrips = (K.nx + wout - 1) / wout;

@@ -16,6 +16,8 @@ hipError_t launch_derived(const StepConsts& K, const double* f, double* out, uin
 int diag_blocks(const StepConsts& K);
 hipError_t launch_diagnostics(const StepConsts& K, const double* f, double* partials, double* out8, hipStream_t s);
 hipError_t launch_pack(const StepConsts& K, const double* f, double* dense, hipStream_t s);
+// streaming copy of bytes (a multiple of 16) with 16-byte loads and stores
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_unpack(const StepConsts& K, const double* dense, double* f, hipStream_t s);
 hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew,
                              hipStream_t s);

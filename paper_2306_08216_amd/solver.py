@@ -30,9 +30,13 @@ def params_of(prob: Problem, keep: list) -> L.mdf_params:
         a = np.ascontiguousarray(a, dtype=np.float64)
         keep.append(a)
         return a.ctypes.data_as(C.POINTER(C.c_double))
+    for f in (prob.force_x, prob.force_y):
+        if f is not None and np.shape(f) != (prob.ny, prob.nx):
+            raise ValueError("force fields must have shape (ny, nx)")
     return L.mdf_params(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                         prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
-                        prob.fx, prob.fy, arr(prob.inv_dx_x), arr(prob.inv_dx_y), prob.dx_min)
+                        prob.fx, prob.fy, arr(prob.inv_dx_x), arr(prob.inv_dx_y), prob.dx_min,
+                        arr(prob.force_x), arr(prob.force_y))
 
 
 class Solver:

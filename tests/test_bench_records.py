@@ -38,7 +38,8 @@ def test_traffic_needs_matching_choice(bench):
 def test_digest_covers_the_step_sources(bench, tmp_path, monkeypatch):
     """Changing any of the step's sources changes the digest."""
     import shutil
-    files = ("mdf_fused.hip", "mdf_fused2.hip", "mdf_device.hpp", "mdf_internal.hpp", "mdf_api.hip")
+    files = tuple(bench.step_sources())
+    assert "mdf_fused_impl.hpp" in files and "mdf_fused_w256p.hip" in files and "mdf_api.hip" in files
     d = tmp_path / "csrc"
     d.mkdir()
     for f in files:

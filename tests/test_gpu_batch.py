@@ -165,21 +165,27 @@ def test_autotune_restores_state_and_caches(gpu, tmp_path):
 
 def test_full_batch_config_sampled(gpu):
     """256 instances (sizes 64..512, nu log-uniform in [1e-3, 1e-1], k^-3 fields,
-    seed 20230614) in one launch per step; 8 sampled instances vs the oracle."""
+    seed 20230614) in the benchmark's launch configuration (the tuning cache's
+    choice, graph replay); 8 sampled instances vs the oracle after 20 steps."""
+    import os
     from oracle.orc import Oracle
     inst = P.batch_instances(256, seed=20230614)
     probs = [P.random_vortex(n, sd, nu) for n, nu, sd in inst]
-    steps = 3
+    steps = 20
     say(f"[gpu batch] full config count=256 nodes={sum(p.nx * p.ny for p in probs)} steps={steps}")
     b = gpu(probs)
-    b.step(steps)
+    tuning = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2306_08216_amd",
+                          "tuning_mi355x.json")
+    choice, cached = b.autotune(tuning, steps=5)
+    say(f"    choice={choice} from_cache={cached}")
+    b.step_graph(steps)
     sizes = np.array([p.nx for p in probs])
     picks = []
     for n in (64, 128, 256, 512):
         idx = np.nonzero(sizes == n)[0]
         picks += [int(idx[0]), int(idx[-1])]
     for i in picks:
-        o = Oracle(probs[i])
+        o = Oracle(probs[i], threads=8)
         o.step(steps)
         err = np.abs(b.save(i).cpu().numpy() - o.f()).max()
         say(f"    instance {i} n={probs[i].nx} nu={probs[i].nu:.3g} max|df|={err:.3e}")
@@ -248,4 +254,39 @@ def test_batch_zero_steps_keep_the_initial_state(gpu):
         err = np.abs(b.save(i).cpu().numpy() - Oracle(p).f()).max()
         say(f"    instance {i} {p.nx}x{p.ny} max|df|={err:.3e}")
         assert err <= TOL
+    b.close()
+
+
+def test_batch_instance_derived_and_diagnostics(gpu):
+    """Per-instance local quantities (Sec. 2.4) and diagnostics of a batch
+    against each instance's oracle run (bounds propagated from the state
+    tolerance through the division by nu + c_s^2 dt/2, as for single runs)."""
+    from oracle.orc import Oracle
+    probs = _mixed()
+    steps = 30
+    say(f"[gpu batch] derived and diagnostics, sizes={[p.nx for p in probs]} steps={steps}")
+    b = gpu(probs)
+    b.step(steps)
+    for i in (0, 4, 8, 9):
+        p = probs[i]
+        o = Oracle(p)
+        o.step(steps)
+        do = o.derived()
+        d = b.derived(i).cpu().numpy()
+        theta = 0.2 * p.c ** 2 * o.dt
+        base = 8 * TOL * p.c / (p.nu + theta)
+        for k in range(14):
+            bound = base * (2 if k == 4 else 1) * (2 * p.nu if k in (8, 9, 10) else 1) + 1e-13 * np.abs(do[k]).max()
+            assert np.abs(d[k] - do[k]).max() <= bound, (i, k)
+        sub = b.derived(i, (1 << 12) | (1 << 3)).cpu().numpy()
+        assert np.abs(sub[0] - do[3]).max() <= base and np.abs(sub[1] - do[12]).max() <= base
+        diag, status = b.diagnostics(i)
+        dio = o.diagnostics()
+        assert status == 0 and diag[6] == 0.0
+        # sums over n nodes in different orders differ by up to n ulps
+        sum_rel = p.nodes * 2.0 ** -52
+        assert abs(diag[2] - dio[2]) <= 10 * TOL * np.sqrt(2 * dio[2] * dio[7]) + sum_rel * dio[2]
+        assert abs(diag[4] - dio[4]) <= 10 * TOL and diag[7] == pytest.approx(dio[7], rel=sum_rel)
+        assert abs(diag[5] - dio[5]) <= 10 * TOL * p.nx / p.lx
+        say(f"    instance {i} n={p.nx}: derived and diagnostics agree")
     b.close()

@@ -1,0 +1,115 @@
+"""GPU parity at the benchmark's full sizes and in the launch configuration
+the benchmark times (the kernel choice the tuning cache holds for the
+workload on this device, applied through Solver.tuned), against the oracle
+node by node.  The oracle runs on its OpenMP build (identical results)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2306_08216_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNING = os.path.join(ROOT, "paper_2306_08216_amd", "tuning_mi355x.json")
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_08216_amd.solver import Solver
+    return Solver
+
+
+def _wall_field(n, seed, amp):
+    """Smooth velocity field vanishing on the walls of [0,1]^2 (sine modes)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(n) / (n - 1)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u = np.zeros((n, n))
+    v = np.zeros((n, n))
+    for _ in range(6):
+        kx, ky = rng.integers(1, 5, size=2)
+        a, b = rng.normal(size=2) * amp / 3
+        u += a * np.sin(np.pi * kx * X) * np.sin(np.pi * ky * Y)
+        v += b * np.sin(np.pi * ky * X) * np.sin(np.pi * kx * Y)
+    return u, v
+
+
+def _check_tuned(Solver, prob, steps, label):
+    from oracle.orc import Oracle
+    s = Solver(prob, device="cuda:0")
+    choice, cached = s.tuned(TUNING, steps=10)
+    say(f"[gpu full-size] {label}: choice={choice} from_cache={cached}, {steps} steps")
+    assert s.steps == 0
+    s.step(steps)
+    f = s.save().cpu().numpy()
+    s.close()
+    o = Oracle(prob, threads=THREADS)
+    o.step(steps)
+    err = np.abs(f - o.f()).max()
+    say(f"    max|df|={err:.3e} max|f|={np.abs(f).max():.3e}")
+    assert np.all(np.isfinite(f))
+    assert err <= TOL
+    return choice
+
+
+def test_cavity_1024_benchmark_choice(gpu):
+    prob = P.cavity(1024, re=1000.0, lid=0.1)
+    prob.u0, prob.v0 = _wall_field(1024, 3, 0.02)
+    _check_tuned(gpu, prob, 3, "cavity Re 1000 1024^2")
+
+
+def test_cavity_2048_benchmark_choice(gpu):
+    prob = P.cavity(2048, re=1000.0, lid=0.1)
+    prob.u0, prob.v0 = _wall_field(2048, 4, 0.02)
+    _check_tuned(gpu, prob, 2, "cavity Re 1000 2048^2")
+
+
+@pytest.mark.parametrize("pl_n", [0.5, 1.5])
+def test_powerlaw_2048_benchmark_choice(gpu, pl_n):
+    """The stretched 2048^2 power-law cavity at its own clamp [1e-2, 1e2] nu_ref."""
+    prob = P.powerlaw_cavity(2048, pl_n=pl_n)
+    assert prob.nu_max == pytest.approx(100 * 0.1 / 100.0) and prob.nu_min == pytest.approx(1e-2 * 0.1 / 100.0)
+    prob.u0, prob.v0 = _wall_field(2048, 13, 0.05)
+    _check_tuned(gpu, prob, 2, f"power-law cavity n={pl_n} 2048^2")
+
+
+@pytest.mark.parametrize("pl_n", [0.5, 1.5])
+def test_powerlaw_2048_sheared_state(gpu, pl_n):
+    """The benchmark's own regime: 1000 steps from rest on the GPU (the lid
+    has sheared the corners, where the viscosity reaches its clamp), then the
+    state is handed to the oracle and both take 2 more steps."""
+    import torch
+    from oracle.orc import Oracle
+    prob = P.powerlaw_cavity(2048, pl_n=pl_n)
+    s = gpu(prob, device="cuda:0")
+    choice, _ = s.tuned(TUNING, steps=10)
+    say(f"[gpu full-size] power-law n={pl_n} 2048^2 from rest: 1000 steps, choice={choice}")
+    s.step(1000)
+    diag, status = s.diagnostics()
+    assert status == 0 and np.all(np.isfinite(diag))
+    f0 = s.save().cpu().numpy()
+    nu = s.derived(1 << 13).cpu().numpy()[0]
+    say(f"    nu range [{nu.min():.3e}, {nu.max():.3e}], clamp [{prob.nu_min:.1e}, {prob.nu_max:.1e}]")
+    s.step(2)
+    f = s.save().cpu().numpy()
+    s.close()
+    o = Oracle(prob, threads=THREADS)
+    o.set_f(f0)
+    o.step(2)
+    err = np.abs(f - o.f()).max()
+    say(f"    max|df|={err:.3e}")
+    assert err <= TOL
+    del torch

@@ -228,22 +228,59 @@ def test_derived_and_diagnostics(gpu, key):
     s.step(steps)
     d = s.derived().cpu().numpy()
     do = o.derived()
+    bound = derived_bounds(prob, o, do)
     for k in range(14):
-        scale = max(np.abs(do[k]).max(), 1e-30)
         err = np.abs(d[k] - do[k]).max()
-        assert err <= 1e-9 * scale + 1e-13, (k, err, scale)
+        assert err <= bound[k], (k, err, bound[k])
     # a subset in mask order
     mask = (1 << 1) | (1 << 6) | (1 << 12)
     sub = s.derived(mask).cpu().numpy()
-    np.testing.assert_allclose(sub, do[[1, 6, 12]], rtol=1e-9, atol=1e-13)
+    for i, k in enumerate((1, 6, 12)):
+        assert np.abs(sub[i] - do[k]).max() <= bound[k]
     diag, status = s.diagnostics()
     dio = o.diagnostics()
     assert status == 0
-    np.testing.assert_allclose(diag[[2, 3, 4, 5, 7]], dio[[2, 3, 4, 5, 7]], rtol=1e-9)
+    # bounds propagated from the state tolerance: a moment sums five
+    # components (error <= 5 TOL); KE moves by at most sum |u| |du| dA <=
+    # 10 TOL sqrt(2 KE area) (Cauchy-Schwarz); enstrophy by max|omega| times the
+    # vorticity bound times the area; the central-difference divergence by
+    # 10 TOL times the largest 1/dx
+    area = dio[7]
+    sum_rel = prob.nodes * 2.0 ** -52         # sums over n nodes in different orders: up to n ulps
+    assert abs(diag[2] - dio[2]) <= 10 * TOL * np.sqrt(2 * dio[2] * area) + sum_rel * dio[2] + 1e-30
+    assert abs(diag[4] - dio[4]) <= 10 * TOL
+    assert diag[7] == pytest.approx(dio[7], rel=sum_rel)
+    assert abs(diag[3] - dio[3]) <= 2 * np.abs(do[12]).max() * bound[12] * area + sum_rel * dio[3] + 1e-30
+    gmax = prob.cfl / (prob.c * o.dt)          # largest 1/dx, since dt = cfl dx_min / c
+    assert abs(diag[5] - dio[5]) <= 10 * TOL * gmax
     assert abs(diag[0] - dio[0]) <= 1e-12 * max(1.0, np.abs(o.moments()[0]).sum())
     assert abs(diag[1] - dio[1]) <= 1e-12 * max(1.0, np.abs(o.moments()[1]).sum())
     assert diag[6] == 0.0
     s.close()
+
+
+def derived_bounds(prob, o, do):
+    """Largest admissible |GPU - oracle| per derived plane, propagated from the
+    state tolerance: every plane is a sum of two differences of f_hat - f^eq
+    (|c_j| = c), each within 2 TOL, divided by nu + c_s^2 dt/2 (eq. 2.4.1 from
+    the stored state); the stress planes carry the factor 2 nu (eq. 2.4.4),
+    the viscosity plane is compared relatively (its root is solved to
+    rounding).  The division by nu + theta amplifies the state's rounding, by
+    up to 1e3 in the low-viscosity runs here, which is why these planes are
+    not held to the state's 1e-12."""
+    nu_plane = do[13]
+    theta = 0.2 * prob.c ** 2 * o.dt
+    amp = 1.0 / (nu_plane.min() + theta)
+    base = 8 * TOL * prob.c * amp
+    b = [base] * 14
+    for k in (4,):
+        b[k] = 2 * base                         # div u: four differences
+    for k in (8, 9, 10):
+        b[k] = base * 2 * nu_plane.max()
+    b[13] = 1e-12 * nu_plane.max()
+    # a power-law viscosity agrees to ~1e-13 relative, which moves every plane
+    # relatively by as much
+    return [bk + 1e-12 * np.abs(do[k]).max() for k, bk in enumerate(b)]
 
 
 def test_save_load_resume_and_determinism(gpu):
