@@ -197,6 +197,19 @@ int32_t    mdf_cnn_param_count(void);
 size_t     mdf_cnn_workspace_size(int32_t batch, int32_t h, int32_t w);
 mdf_status mdf_cnn_forward(void* ws, size_t ws_bytes, const float* params, int32_t batch, int32_t h, int32_t w,
                            const double* uv, double in_scale, double out_scale, double* duv, void* hip_stream);
+/* The forward pass of mdf_cnn_forward for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument; the activations live in a fixed device
+ * array of the library (about 10 MiB per GPU, held until the process ends),
+ * so batch*h*w may not exceed MDF_CNN_NOALLOC_MAX_PIXELS (one 128 x 128
+ * field); larger inputs are MDF_EINVAL.  Same arguments, rounding and results
+ * as mdf_cnn_forward; calls no allocator.  Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other host
+ * threads) race; the array keeps the last call's contents, none of which a
+ * call reads before writing it.  Asynchronous on hip_stream. */
+#define MDF_CNN_NOALLOC_MAX_PIXELS 16384
+mdf_status mdf_cnn_forward_noalloc(const float* params, int32_t batch, int32_t h, int32_t w, const double* uv,
+                                   double in_scale, double out_scale, double* duv, void* hip_stream);
 /* Gradient of L = mean((y - target/out_scale)^2) over pixels and both
  * channels with respect to every parameter, into grad (DEVICE FP32, one
  * value per parameter), for the activations of the last forward call on ws;

@@ -60,6 +60,8 @@ SIGNATURES = {
     "mdf_cnn_workspace_size": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "mdf_cnn_forward": (C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                   C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "mdf_cnn_forward_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_double,
+                                          C.c_double, C.c_void_p, C.c_void_p]),
     "mdf_cnn_backward": (C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                    C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mdf_cnn_layer_io": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
@@ -299,6 +301,12 @@ def mdf_cnn_forward(ws: int, ws_bytes: int, params: int, batch: int, h: int, w: 
                     out_scale: float, duv: int, stream: int):
     return check(lib().mdf_cnn_forward(ws, ws_bytes, params, int(batch), int(h), int(w), uv, float(in_scale),
                                        float(out_scale), duv, stream))
+
+
+def mdf_cnn_forward_noalloc(params: int, batch: int, h: int, w: int, uv: int, in_scale: float, out_scale: float,
+                            duv: int, stream: int):
+    return check(lib().mdf_cnn_forward_noalloc(params, int(batch), int(h), int(w), uv, float(in_scale),
+                                               float(out_scale), duv, stream))
 
 
 def mdf_cnn_backward(ws: int, ws_bytes: int, params: int, batch: int, h: int, w: int, target: int,

@@ -869,6 +869,20 @@ mdf_status mdf_cnn_forward(void* ws, size_t ws_bytes, const float* params, int32
                                                (hipStream_t)hip_stream), "closure forward");
 }
 
+mdf_status mdf_cnn_forward_noalloc(const float* params, int32_t batch, int32_t h, int32_t w, const double* uv,
+                                   double in_scale, double out_scale, double* duv, void* hip_stream)
+{
+    if (mdf_cnn_workspace_size(batch, h, w) == 0)
+        return fail(nullptr, MDF_EINVAL, "batch >= 1, h >= 3 and w a multiple of 32 required");
+    if ((int64_t)batch * h * w > MDF_CNN_NOALLOC_MAX_PIXELS ||
+        mdf::cnn_noalloc_bytes(batch, h, w) > mdf::cnn_noalloc_capacity())
+        return fail(nullptr, MDF_EINVAL, "batch*h*w = %lld exceeds the fixed scratch of %d pixels",
+                    (long long)batch * h * w, MDF_CNN_NOALLOC_MAX_PIXELS);
+    if (!params || !uv || !duv) return fail(nullptr, MDF_EINVAL, "params, uv and duv must be non-NULL");
+    return hip_check(nullptr, mdf::cnn_forward_noalloc(params, batch, h, w, uv, in_scale, out_scale, duv,
+                                                       (hipStream_t)hip_stream), "closure forward (no allocation)");
+}
+
 mdf_status mdf_cnn_backward(void* ws, size_t ws_bytes, const float* params, int32_t batch, int32_t h, int32_t w,
                             const double* duv_target, double out_scale, float* grad, double* loss, void* hip_stream)
 {

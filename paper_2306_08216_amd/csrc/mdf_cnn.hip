@@ -12,6 +12,8 @@
 // the same kernel for the data gradient (taps mirrored, channels transposed)
 // and a second MFMA GEMM over pixels for the weight gradient, reduced in a
 // fixed order (no atomics: results are bitwise reproducible).
+#include <mutex>
+
 #include "mdf_device.hpp"
 #include "mdf_internal.hpp"
 
@@ -515,12 +517,56 @@ hipError_t forward_at(const CnnLayout& L, char* ws, const float* params, int B, 
     return hipGetLastError();
 }
 
+// Scratch of the forward pass for callers that cannot allocate: a fixed
+// device array (one copy per GPU, held until the process ends) sized for the
+// inference layout of up to kNoAllocPixels pixels.  Host code never passes
+// the array's name to a kernel: it is a host-side stand-in, and its device
+// address is looked up once per device with that device current.
+constexpr size_t kNoAllocBytes = (size_t)10 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 hipError_t cnn_forward(char* ws, const float* params, int B, int H, int W, const double* uv, double in_scale,
                        double out_scale, double* duv, hipStream_t s)
 {
     return forward_at(cnn_layout(B, H, W), ws, params, B, H, W, uv, in_scale, out_scale, duv, s);
+}
+
+size_t cnn_noalloc_capacity() { return kNoAllocBytes; }
+
+size_t cnn_noalloc_bytes(int B, int H, int W) { return cnn_layout(B, H, W, false).total; }
+
+hipError_t cnn_forward_noalloc(const float* params, int B, int H, int W, const double* uv, double in_scale,
+                               double out_scale, double* duv, hipStream_t s)
+{
+    const CnnLayout L = cnn_layout(B, H, W, false);
+    if (L.total > kNoAllocBytes) return hipErrorInvalidValue;
+    void* ws = nullptr;
+    const hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess) return e;
+    return forward_at(L, (char*)ws, params, B, H, W, uv, in_scale, out_scale, duv, s);
 }
 
 hipError_t cnn_backward(char* ws, const float* params, int B, int H, int W, const double* duv_t, double out_scale,

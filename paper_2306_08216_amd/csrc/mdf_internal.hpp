@@ -76,6 +76,12 @@ int32_t cnn_param_count();
 size_t cnn_workspace_size(int B, int H, int W);
 hipError_t cnn_forward(char* ws, const float* params, int B, int H, int W, const double* uv, double in_scale,
                        double out_scale, double* duv, hipStream_t s);
+// The forward pass on the library's fixed device scratch (no allocation);
+// cnn_noalloc_bytes(B, H, W) must not exceed cnn_noalloc_capacity().
+size_t cnn_noalloc_capacity();
+size_t cnn_noalloc_bytes(int B, int H, int W);
+hipError_t cnn_forward_noalloc(const float* params, int B, int H, int W, const double* uv, double in_scale,
+                               double out_scale, double* duv, hipStream_t s);
 hipError_t cnn_backward(char* ws, const float* params, int B, int H, int W, const double* duv_t, double out_scale,
                         float* grad, double* loss_dev, hipStream_t s);
 hipError_t cnn_layer_io(const char* ws, int B, int H, int W, int layer, unsigned short* in_bf16, float* z_f32,
