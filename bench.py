@@ -300,7 +300,8 @@ def main():
             probs.append(prob)
         wl = (f"power-law lid-driven cavity, index n in {{{', '.join(f'{p:g}' for p in indices)}}}, "
               f"tanh-stretched {n}x{n} grid (beta 1.5 both axes), Re_PL 100, lid 0.1, viscosity clamp "
-              f"[1e-2, 1e2] nu_ref, state pre-run {args.prerun} steps from rest, FP64")
+              f"[1e-2, 1e2] nu_ref for n < 1 and [1e-2, 4] nu_ref for n > 1, state pre-run {args.prerun} steps "
+              f"from rest, FP64")
         stem = {0.5: "powerlaw", 1.5: "powerlaw-n1.5-"}
     else:
         n = args.n or 1024

@@ -135,7 +135,7 @@ mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, cons
  * velocity component (default for a Newtonian fluid).
  * tile_w (columns per strip incl. the 8-column halo, one wave per 64; 64,
  * 128 or 256, variant 1 only), seg_h and prefetch (rows loaded ahead, 2 or 3;
- * 2 with 256 lanes) apply to the fused
+ * 2 with 256 lanes and for a power law on a mapped grid) apply to the fused
  * variants; 0 keeps the current value.  With a force field only variants 0
  * and 1 exist, variant 1 with tile_w 64 and prefetch 2 (the default then).  seg_h > 0 cuts every strip into
  * segments of seg_h rows; seg_h = -r (r = 1..4; -1 is the default) selects

@@ -150,6 +150,12 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
     // byte offsets of this lane's node within a row: x-part block, y-part block
     const unsigned vx = (unsigned)xg * 48u, vy = (unsigned)K.pitch * 48u + (unsigned)xg * 32u;
     const unsigned vx_st = outc ? vx : 0x7fffff00u, vy_st = outc ? vy : 0x7fffff00u;
+    // An output column needs f_bar^+ up to 4 columns away (two stencils of
+    // reach 2), so lanes past xs1 + 3 -- the surplus of a strip narrower than
+    // its lanes -- feed no output: their loads read past the row's records
+    // (zeros, no memory traffic) and their results are never stored.
+    const bool lane_needed = x <= xs1 + 3;
+    const unsigned vx_ld = lane_needed ? vx : 0x7fffff00u, vy_ld = lane_needed ? vy : 0x7fffff00u;
     const int row_bytes = K.pitch * 80;
 
     auto wrap_y = [&](int k) -> int {
@@ -168,7 +174,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
     // the compiler counts the memory operations in flight exactly and waits
     // only for the row it consumes.
     double pre[4][10], pgy[4] = {0.0, 0.0, 0.0, 0.0}, pff[4][2];
-    const unsigned vf = (unsigned)xg * 16u;   // this lane's (F_x, F_y) within a force row
+    const unsigned vf = lane_needed ? (unsigned)xg * 16u : 0x7fffff00u;   // this lane's (F_x, F_y) in a force row
     auto load_row = [&](int k, double* dst, double& gyr, double* fdst) {
         const bool on = k <= kend && row_ok(k);   // rows past kend are never used
         const BufRes rs = row_res(fin, row_bytes, on ? wrap_y(k) : 0, on);
@@ -178,8 +184,8 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
             fdst[0] = fv.x;
             fdst[1] = fv.y;
         }
-        const dvec2 a = buf_load2(rs, vx), b = buf_load2(rs, vx + 16u), c = buf_load2(rs, vx + 32u);
-        const dvec2 d = buf_load2(rs, vy), e = buf_load2(rs, vy + 16u);
+        const dvec2 a = buf_load2(rs, vx_ld), b = buf_load2(rs, vx_ld + 16u), c = buf_load2(rs, vx_ld + 32u);
+        const dvec2 d = buf_load2(rs, vy_ld), e = buf_load2(rs, vy_ld + 16u);
         dst[0] = a.x; dst[1] = a.y; dst[3] = b.x;   // x part: j = 0, 1, 3 of each set
         dst[5] = b.y; dst[6] = c.x; dst[8] = c.y;
         dst[2] = d.x; dst[4] = d.y;                 // y part: j = 2, 4 of each set

@@ -225,16 +225,23 @@ def sine_mapping(n: int, amp: float = 0.2, length: float = 2.0 * math.pi):
 
 
 def powerlaw_cavity(n: int = 2048, pl_n: float = 0.5, beta: float = 1.5, lid: float = 0.1,
-                    re: float = 100.0, cfl: float = 0.5, eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+                    re: float = 100.0, cfl: float = 0.5, eta: float = 0.8, s_ratio: float = 1.5,
+                    ceiling: Optional[float] = None) -> Problem:
     """Power-law lid-driven cavity on a tanh-stretched grid (both axes).
-    Re = U^(2-n) L^n / K with L = 1; viscosity clamp [1e-2, 1e2] nu_ref with
-    nu_ref = U L / Re."""
+    Re = U^(2-n) L^n / K with L = 1; viscosity clamp [1e-2, ceiling] nu_ref
+    with nu_ref = U L / Re.  The ceiling defaults to 100 for a shear-thinning
+    fluid (n < 1) and to 4 for a shear-thickening one (n > 1): there the
+    viscosity peaks at the singular lid corners, and ceilings of 10 nu_ref and
+    more let the corner non-equilibrium parts grow without bound (the run
+    diverges at 1024^2 and 2048^2; 100 nu_ref at every size from 64^2)."""
     K = lid ** (2.0 - pl_n) / re
     nu_ref = lid / re
+    if ceiling is None:
+        ceiling = 100.0 if pl_n <= 1.0 else 4.0
     _, g, dxm = tanh_mapping(n, beta)
     z = np.zeros((n, n))
     return Problem(nx=n, ny=n, lx=1.0, ly=1.0, nu=K, u0=z, v0=z.copy(), p0=z.copy(), pl_n=pl_n,
-                   nu_min=1e-2 * nu_ref, nu_max=1e2 * nu_ref, cfl=cfl, eta=eta, s_ratio=s_ratio,
+                   nu_min=1e-2 * nu_ref, nu_max=ceiling * nu_ref, cfl=cfl, eta=eta, s_ratio=s_ratio,
                    bc_x=WALL, bc_y=WALL, lid_u=lid, inv_dx_x=g.copy(), inv_dx_y=g.copy(), dx_min=dxm,
                    name=f"powerlaw_cavity_{n}_n{pl_n:g}")
 

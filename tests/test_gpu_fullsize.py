@@ -79,9 +79,11 @@ def test_cavity_2048_benchmark_choice(gpu):
 
 @pytest.mark.parametrize("pl_n", [0.5, 1.5])
 def test_powerlaw_2048_benchmark_choice(gpu, pl_n):
-    """The stretched 2048^2 power-law cavity at its own clamp [1e-2, 1e2] nu_ref."""
+    """The stretched 2048^2 power-law cavity at its own clamp: [1e-2, 1e2] nu_ref
+    for n = 0.5, [1e-2, 4] nu_ref for n = 1.5."""
     prob = P.powerlaw_cavity(2048, pl_n=pl_n)
-    assert prob.nu_max == pytest.approx(100 * 0.1 / 100.0) and prob.nu_min == pytest.approx(1e-2 * 0.1 / 100.0)
+    nu_ref = 0.1 / 100.0
+    assert prob.nu_max == pytest.approx((100 if pl_n < 1 else 4) * nu_ref) and prob.nu_min == pytest.approx(1e-2 * nu_ref)
     prob.u0, prob.v0 = _wall_field(2048, 13, 0.05)
     _check_tuned(gpu, prob, 2, f"power-law cavity n={pl_n} 2048^2")
 
@@ -109,7 +111,11 @@ def test_powerlaw_2048_sheared_state(gpu, pl_n):
     o = Oracle(prob, threads=THREADS)
     o.set_f(f0)
     o.step(2)
-    err = np.abs(f - o.f()).max()
-    say(f"    max|df|={err:.3e}")
-    assert err <= TOL
+    fo = o.f()
+    d = np.abs(f - fo)
+    say(f"    max|df|={d.max():.3e} max|f|={np.abs(fo).max():.3e}")
+    # For n = 3/2 the lid corners, where nu sits at its ceiling (27 c dx_min),
+    # hold non-equilibrium parts of order 10-20: where |f| exceeds 1 the bar
+    # is the state tolerance relative to the local magnitude (a few ulps).
+    assert np.all(d <= TOL * np.maximum(1.0, np.abs(fo)))
     del torch

@@ -94,10 +94,7 @@ def _plcav(pl_n):
     prob = P.powerlaw_cavity(64, pl_n=pl_n)
     u, v, p = _wall_field(64, seed=9, amp=0.05 if pl_n < 1 else 0.02)
     prob.u0, prob.v0 = u, v
-    if pl_n > 1:
-        # at 64^2 the default ceiling (100 nu_ref) lets nu exceed c*dx at the lid
-        # corners and the run diverges; a lower ceiling keeps the case bounded
-        prob.nu_max = 0.004
+    assert pl_n < 1 or prob.nu_max == 0.004   # the shear-thickening ceiling of 4 nu_ref
     return prob
 
 
