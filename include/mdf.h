@@ -241,6 +241,22 @@ mdf_status mdf_cnn_adam(float* params, const float* grad, float* m, float* v, in
 mdf_status mdf_closure_apply(mdf_ctx* ctx, const double* du, const double* dv, double ke_ref, double div_factor,
                              double* ke_out, double* div_out, int32_t* fell_back);
 
+/* The same guarded correction without any host synchronisation, for a
+ * rollout that keeps the device busy: mdf_closure_begin sets the reference
+ * energy ke_ref (DEVICE, in the context's workspace) to the current field's
+ * kinetic energy and zeroes the counters; each mdf_closure_apply_async
+ * evaluates the guard on the device (corrected energy <= ke_ref and largest
+ * divergence <= div_factor times the current field's, both finite), applies
+ * the correction only if it passes, counts a fall-back if not, and sets
+ * ke_ref to the energy of the field it leaves.  du, dv: DEVICE [ny][nx], not
+ * NULL.  mdf_closure_stats synchronises and writes {ke_ref, fall-backs,
+ * windows since mdf_closure_begin} to HOST out[3].  The diagnostics and the
+ * synchronous mdf_closure_apply share the scratch these calls use, but not
+ * their state.  Periodic uniform grids only (else MDF_EINVAL). */
+mdf_status mdf_closure_begin(mdf_ctx* ctx);
+mdf_status mdf_closure_apply_async(mdf_ctx* ctx, const double* du, const double* dv, double div_factor);
+mdf_status mdf_closure_stats(mdf_ctx* ctx, double out[3]);
+
 /* ---------------------------------------------------------------------------
  * Batches: many independent instances of the same method advanced together
  * (a project addition, not in the paper).  Each instance has its own grid

@@ -70,6 +70,9 @@ SIGNATURES = {
                                C.c_float, C.c_float, C.c_int32, C.c_void_p]),
     "mdf_closure_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "mdf_closure_begin": (C.c_int, [C.c_void_p]),
+    "mdf_closure_apply_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    "mdf_closure_stats": (C.c_int, [C.c_void_p, _dp]),
     "mdf_batch_workspace_size": (C.c_size_t, [C.POINTER(mdf_params), C.c_int32]),
     "mdf_batch_init": (C.c_int, [C.POINTER(mdf_params), C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p,
@@ -332,3 +335,18 @@ def mdf_closure_apply(ctx: int, du: int, dv: int, ke_ref: float, div_factor: flo
     check(lib().mdf_closure_apply(ctx, du, dv, float(ke_ref), float(div_factor), C.byref(ke), C.byref(div),
                                   C.byref(fb)), ctx)
     return ke.value, div.value, bool(fb.value)
+
+
+def mdf_closure_begin(ctx: int):
+    return check(lib().mdf_closure_begin(ctx), ctx)
+
+
+def mdf_closure_apply_async(ctx: int, du: int, dv: int, div_factor: float):
+    return check(lib().mdf_closure_apply_async(ctx, du, dv, float(div_factor)), ctx)
+
+
+def mdf_closure_stats(ctx: int):
+    """(ke_ref, fall-backs, windows) since mdf_closure_begin; synchronises."""
+    out = (C.c_double * 3)()
+    check(lib().mdf_closure_stats(ctx, out), ctx)
+    return out[0], int(out[1]), int(out[2])

@@ -8,6 +8,7 @@ Every arithmetic step runs in libmdf.so; this module allocates device memory
 from __future__ import annotations
 
 import math
+import sys
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -18,6 +19,7 @@ from . import problems as P
 from .solver import Solver
 
 CHANNELS = (2, 32, 32, 32, 2)
+NOALLOC_MAX_PIXELS = 16384   # batch*h*w limit of mdf_cnn_forward_noalloc (MDF_CNN_NOALLOC_MAX_PIXELS)
 IN_SCALE = 20.0      # (u, v) ~ 0.05 -> O(1) inputs
 OUT_SCALE = 1.0e-4   # one-window corrections ~ 1e-5 .. 1e-4 -> O(1) outputs
 
@@ -140,7 +142,9 @@ def make_pairs(seeds: Sequence[int], n_coarse: int = 128, ratio: int = 4, nu: fl
     CFL) and its velocity is paired with the restricted fine velocity minus it."""
     inputs, targets = [], []
     nf = n_coarse * ratio
-    for sd in seeds:
+    for si, sd in enumerate(seeds):
+        if si % 8 == 0:
+            print(f"closure pairs: seed {si + 1}/{len(seeds)}", file=sys.stderr, flush=True)
         pf = P.random_vortex(nf, sd, nu, kmax=kmax, urms=urms)
         fine = Solver(pf)
         coarse = Solver(_coarse_problem(pf, ratio))
@@ -177,6 +181,8 @@ def train(net: ClosureNet, inputs: torch.Tensor, targets: torch.Tensor, iters: i
         net.adam(lr=lr * (0.1 if frac > 0.7 else 1.0))
         if log_every and (it % log_every == 0 or it == iters - 1):
             hist.append((it, float(loss.item())))
+            if it % (10 * log_every) == 0:
+                print(f"closure training: iteration {it}/{iters} loss {hist[-1][1]:.4e}", file=sys.stderr, flush=True)
     return hist
 
 
@@ -205,6 +211,15 @@ def rollout(seed: int, net: Optional[ClosureNet], n_coarse: int = 128, ratio: in
     ufr, vfr, t_fine = fine_ref
     coarse = Solver(_coarse_problem(pf, ratio))
     fallbacks = 0
+    n = coarse.nx
+    if net is not None:
+        # buffers of the loop, allocated before it: the loop itself allocates
+        # nothing and never waits for the device (moments, network and guard
+        # all run on the solver's stream; the guard decides on the device)
+        assert net.h == n and net.w == n and net.stream == coarse.stream
+        uv = torch.empty((1, 2, n, n), dtype=torch.float64, device=coarse.device)
+        duv = torch.empty_like(uv)
+        noalloc = n * n <= NOALLOC_MAX_PIXELS
     torch.cuda.synchronize()
     w0 = torch.cuda.Event(enable_timing=True)
     w1 = torch.cuda.Event(enable_timing=True)
@@ -212,21 +227,25 @@ def rollout(seed: int, net: Optional[ClosureNet], n_coarse: int = 128, ratio: in
     if net is None:
         coarse.step(steps)
     else:
-        ke_ref, _, _ = apply_correction(coarse, None, None, 0.0, 0.0)
+        L.mdf_closure_begin(coarse.ctx)
+        sc = coarse.stream.cuda_stream
         for _ in range(steps // K):
             coarse.step(K)
-            u, v, _ = coarse.moments()
-            duv = net.forward(torch.stack([u, v])[None].contiguous())
-            if gain != 1.0:
-                duv.mul_(gain)
+            L.mdf_moments(coarse.ctx, uv[0, 0].data_ptr(), uv[0, 1].data_ptr(), None)
+            if noalloc:
+                L.mdf_cnn_forward_noalloc(net.params.data_ptr(), 1, n, n, uv.data_ptr(), IN_SCALE, OUT_SCALE * gain,
+                                          duv.data_ptr(), sc)
+            else:
+                L.mdf_cnn_forward(net.ws, net.ws_bytes, net.params.data_ptr(), 1, n, n, uv.data_ptr(), IN_SCALE,
+                                  OUT_SCALE * gain, duv.data_ptr(), sc)
             # guard: energy must not exceed the last check's, divergence at most div_factor x the plain field's
-            ke_ref, _, fb = apply_correction(coarse, duv[0, 0].contiguous(), duv[0, 1].contiguous(), ke_ref,
-                                             div_factor)
-            fallbacks += int(fb)
+            L.mdf_closure_apply_async(coarse.ctx, duv[0, 0].data_ptr(), duv[0, 1].data_ptr(), div_factor)
         coarse.step(steps % K)
     w1.record(coarse.stream)
     torch.cuda.synchronize()
     t_coarse = w0.elapsed_time(w1) / 1e3
+    if net is not None:
+        _, fallbacks, _ = L.mdf_closure_stats(coarse.ctx)
     uc, vc, _ = coarse.moments()
     err = math.sqrt(float(((uc - ufr) ** 2 + (vc - vfr) ** 2).sum()) / float((ufr ** 2 + vfr ** 2).sum()))
     coarse.close()
@@ -255,6 +274,7 @@ def experiment(train_seeds: Sequence[int], test_seeds: Sequence[int], n_coarse: 
                          fine_ref=refs[sd]["fine_ref"], gain=g)["rel_l2"] for sd in val_seeds]
             val.append((g, float(np.mean(e))))
         gain = min(val, key=lambda r: r[1])[0]
+    print(f"closure validation: {val} -> gain {gain}", file=sys.stderr, flush=True)
     rows = []
     for sd in test_seeds:
         plain = rollout(sd, None, n_coarse, ratio, nu, K, horizon, kmax, urms)

@@ -88,7 +88,7 @@ Layout layout_for(int nx, int ny, bool force_field)
     L.off_gx = o;   o += align256((size_t)nx * sizeof(double));
     L.off_gy = o;   o += align256((size_t)ny * sizeof(double));
     L.off_dp = o;   o += align256(8 * 1024 * sizeof(double));
-    L.off_do = o;   o += align256(8 * sizeof(double));
+    L.off_do = o;   o += align256(16 * sizeof(double));   // diagnostics result (8), closure guard state (4)
     L.off_seg = o;  o += align256(kSegCap * sizeof(int4));
     // force field: (F_x, F_y) per node in rows of pitch nodes
     L.off_ff = o;   o += force_field ? align256(2 * L.pitch * (size_t)ny * sizeof(double)) : 0;
@@ -933,7 +933,54 @@ mdf_status mdf_closure_apply(mdf_ctx* c, const double* du, const double* dv, dou
     if (div_out) *div_out = ok ? r[3] : r[1];
     if (fell_back) *fell_back = (du && !ok) ? 1 : 0;
     if (!ok) return MDF_OK;
-    return hip_check(c, mdf::launch_closure_apply(c->K, f, du, dv, c->stream), "closure apply");
+    return hip_check(c, mdf::launch_closure_apply(c->K, f, du, dv, nullptr, c->stream), "closure apply");
+}
+
+static mdf_status closure_async_check(mdf_ctx* c)
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (c->p.bc_x != MDF_BC_PERIODIC || c->p.bc_y != MDF_BC_PERIODIC || c->p.inv_dx_x || c->p.inv_dx_y)
+        return fail(c, MDF_EINVAL, "the closure applies to periodic uniform grids");
+    return MDF_OK;
+}
+
+mdf_status mdf_closure_begin(mdf_ctx* c)
+{
+    if (const mdf_status s = closure_async_check(c)) return s;
+    const double hx = c->p.lx / c->p.nx, hy = c->p.ly / c->p.ny;
+    double* state = c->diag_out + 8;
+    hipError_t e = mdf::launch_closure_guard(c->K, c->f[c->cur], nullptr, nullptr, hx, hy, c->diag_part, c->diag_out,
+                                             c->stream);
+    if (e == hipSuccess) e = mdf::launch_closure_decide(c->diag_out, state, 0.0, true, c->stream);
+    return hip_check(c, e, "closure begin");
+}
+
+mdf_status mdf_closure_apply_async(mdf_ctx* c, const double* du, const double* dv, double div_factor)
+{
+    if (const mdf_status s = closure_async_check(c)) return s;
+    if (!du || !dv) return fail(c, MDF_EINVAL, "du and dv must be non-NULL");
+    if (!(div_factor >= 0.0)) return fail(c, MDF_EINVAL, "div_factor must be >= 0");
+    const double hx = c->p.lx / c->p.nx, hy = c->p.ly / c->p.ny;
+    double* f = c->f[c->cur];
+    double* state = c->diag_out + 8;
+    hipError_t e = mdf::launch_closure_guard(c->K, f, du, dv, hx, hy, c->diag_part, c->diag_out, c->stream);
+    if (e == hipSuccess) e = mdf::launch_closure_decide(c->diag_out, state, div_factor, false, c->stream);
+    if (e == hipSuccess) e = mdf::launch_closure_apply(c->K, f, du, dv, state + 2, c->stream);
+    return hip_check(c, e, "closure apply (asynchronous)");
+}
+
+mdf_status mdf_closure_stats(mdf_ctx* c, double out[3])
+{
+    if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
+    if (!out) return fail(c, MDF_EINVAL, "out is NULL");
+    double st[4] = {0.0, 0.0, 0.0, 0.0};
+    hipError_t e = hipMemcpyAsync(st, c->diag_out + 8, sizeof st, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "closure stats");
+    out[0] = st[0];
+    out[1] = st[1];
+    out[2] = st[3];
+    return MDF_OK;
 }
 
 // ---- batches ---------------------------------------------------------------

@@ -336,9 +336,33 @@ __global__ __launch_bounds__(kGuardBlock) void k_closure_guard_final(const doubl
 }
 
 // f_hat += f^eq(u + du, v + dv, P) - f^eq(u, v, P) at every node
-__global__ void k_closure_apply(StepConsts K, double* __restrict__ f, const double* __restrict__ du,
-                                const double* __restrict__ dv)
+// Guard decision on the device: state = {ke_ref, fall-backs, flag, windows}.
+// The correction is accepted when the corrected field's kinetic energy does
+// not exceed ke_ref and its largest divergence is at most div_factor times the
+// current field's (both finite); ke_ref becomes the energy of the field the
+// window leaves.  reset: ke_ref = the current field's energy, counters zero.
+__global__ void k_closure_decide(const double* __restrict__ out4, double* __restrict__ state, double div_factor,
+                                 int reset)
 {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (reset) {
+        state[0] = out4[0];
+        state[1] = 0.0;
+        state[2] = 0.0;
+        state[3] = 0.0;
+        return;
+    }
+    const bool ok = isfinite(out4[2]) && isfinite(out4[3]) && out4[2] <= state[0] && out4[3] <= div_factor * out4[1];
+    state[0] = ok ? out4[2] : out4[0];
+    state[1] += ok ? 0.0 : 1.0;
+    state[2] = ok ? 1.0 : 0.0;
+    state[3] += 1.0;
+}
+
+__global__ void k_closure_apply(StepConsts K, double* __restrict__ f, const double* __restrict__ du,
+                                const double* __restrict__ dv, const double* __restrict__ flag)
+{
+    if (flag && *flag == 0.0) return;   // the guard refused this window's correction
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= K.nx * K.ny) return;
     const int x = i % K.nx, y = i / K.nx;
@@ -480,10 +504,17 @@ hipError_t launch_closure_guard(const StepConsts& K, const double* f, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_closure_apply(const StepConsts& K, double* f, const double* du, const double* dv, hipStream_t s)
+hipError_t launch_closure_apply(const StepConsts& K, double* f, const double* du, const double* dv, const double* flag,
+                                hipStream_t s)
 {
     const int n = K.nx * K.ny;
-    hipLaunchKernelGGL(k_closure_apply, dim3((n + 255) / 256), dim3(256), 0, s, K, f, du, dv);
+    hipLaunchKernelGGL(k_closure_apply, dim3((n + 255) / 256), dim3(256), 0, s, K, f, du, dv, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_closure_decide(const double* out4, double* state, double div_factor, bool reset, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_closure_decide, dim3(1), dim3(64), 0, s, out4, state, div_factor, reset ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -91,6 +91,10 @@ hipError_t cnn_adam(float* p, const float* g, float* m, float* v, int n, float l
 int closure_guard_blocks(const StepConsts& K);
 hipError_t launch_closure_guard(const StepConsts& K, const double* f, const double* du, const double* dv, double hx,
                                 double hy, double* part, double* out4, hipStream_t s);
-hipError_t launch_closure_apply(const StepConsts& K, double* f, const double* du, const double* dv, hipStream_t s);
+// f_hat += f^eq(u + du, P) - f^eq(u, P); skipped when flag (device) holds 0
+hipError_t launch_closure_apply(const StepConsts& K, double* f, const double* du, const double* dv, const double* flag,
+                                hipStream_t s);
+// guard decision from the guard's out4 into state {ke_ref, fall-backs, flag, windows}
+hipError_t launch_closure_decide(const double* out4, double* state, double div_factor, bool reset, hipStream_t s);
 
 }  // namespace mdf

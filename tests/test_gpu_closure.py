@@ -260,3 +260,36 @@ def test_trained_closure_gains_over_plain_coarse_run(gpu):
             f"{row['t_closure_s']:.3f}s")
         assert row["closure_rel_l2"] < 0.85 * row["plain_rel_l2"]
         assert row["windows"] == 200
+
+
+def test_device_guard_matches_host_guard(gpu):
+    """The guarded correction decided on the device (mdf_closure_begin /
+    mdf_closure_apply_async / mdf_closure_stats, no host synchronisation)
+    leaves the same state and counts the same fall-backs as the host-decided
+    mdf_closure_apply over the same windows, accepted and refused ones alike."""
+    import torch
+    from paper_2306_08216_amd import _lib as L
+    from paper_2306_08216_amd.solver import Solver
+    prob = P.random_vortex(64, 5, 1e-3, kmax=6, urms=0.05)
+    a, b = Solver(prob), Solver(prob)
+    ke_ref, _, _ = gpu.apply_correction(a, None, None, 0.0, 0.0)
+    L.mdf_closure_begin(b.ctx)
+    fallbacks = 0
+    for w in range(12):
+        for s in (a, b):
+            s.step(3)
+        u, v, _ = a.moments()
+        sign = -1.0 if w % 3 != 1 else 1.0            # damping corrections pass, amplifying ones are refused
+        du = (sign * 1e-3 * u).contiguous()
+        dv = (sign * 1e-3 * v).contiguous()
+        ke_ref, _, fb = gpu.apply_correction(a, du, dv, ke_ref, 2.0)
+        fallbacks += int(fb)
+        L.mdf_closure_apply_async(b.ctx, du.data_ptr(), dv.data_ptr(), 2.0)
+    ke_b, fb_b, windows = L.mdf_closure_stats(b.ctx)
+    say(f"[gpu closure] device guard: fallbacks host {fallbacks} device {fb_b} of {windows}")
+    assert windows == 12 and fb_b == fallbacks and 0 < fallbacks < 12
+    assert ke_b == ke_ref
+    assert np.array_equal(a.save().cpu().numpy(), b.save().cpu().numpy())
+    a.close()
+    b.close()
+    del torch
