@@ -326,6 +326,20 @@ const char* mdf_batch_last_error(const mdf_batch* b);     /* never NULL         
 void        mdf_batch_destroy(mdf_batch* b);               /* synchronises; NULL is a no-op    */
 
 /* ---------------------------------------------------------------------------
+ * Von Neumann screen (Sec. 3.1): spectral radius of the growth matrix of one
+ * time step (Steps (1)-(4), the mixed difference of eqs. 2.2.12-2.2.13),
+ * linearised about the uniform state (u0, v0), for the Fourier modes
+ * exp(i (theta_x x/dx + theta_y y/dy)) of a periodic uniform grid with the
+ * spacings lx/nx, ly/ny of p and its nu, cfl, c, eta and s_ratio (Newtonian
+ * only; walls, metrics and forces are not part of the analysis).  theta runs
+ * over nk points per axis on (-pi, pi], theta_i = -pi + 2 pi (i + 1)/nk.
+ * rho (HOST, nk*nk values, row iy then column ix; may be NULL) receives the
+ * radius of each mode; worst (HOST, 3 values) the largest radius and its
+ * (theta_x, theta_y).  A mode is stable when its radius is at most 1.  Host
+ * computation only; MDF_EINVAL for invalid parameters or nk outside 1..4096. */
+mdf_status mdf_stability(const mdf_params* p, double u0, double v0, int32_t nk, double* rho, double* worst);
+
+/* ---------------------------------------------------------------------------
  * Measurement aid (not part of the method): a streaming copy of `bytes`
  * bytes (a multiple of 16; both DEVICE pointers 16-byte aligned, regions not
  * overlapping) with 16-byte loads and stores, asynchronous on hip_stream.  Its

@@ -91,6 +91,7 @@ SIGNATURES = {
     "mdf_batch_last_error": (C.c_char_p, [C.c_void_p]),
     "mdf_batch_destroy": (None, [C.c_void_p]),
     "mdf_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "mdf_stability": (C.c_int, [C.POINTER(mdf_params), C.c_double, C.c_double, C.c_int32, _dp, _dp]),
 }
 
 _lib = None
@@ -350,3 +351,12 @@ def mdf_closure_stats(ctx: int):
     out = (C.c_double * 3)()
     check(lib().mdf_closure_stats(ctx, out), ctx)
     return out[0], int(out[1]), int(out[2])
+
+
+def mdf_stability(p: mdf_params, u0: float, v0: float, nk: int):
+    """(rho[nk, nk], (max rho, theta_x, theta_y)) of the von Neumann screen."""
+    import numpy as np
+    rho = np.empty((int(nk), int(nk)), dtype=np.float64)
+    worst = (C.c_double * 3)()
+    check(lib().mdf_stability(C.byref(p), float(u0), float(v0), int(nk), rho.ctypes.data_as(_dp), worst))
+    return rho, (worst[0], worst[1], worst[2])
