@@ -134,8 +134,8 @@ mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, cons
  * power-law fluid), 2 = fused single-pass strip kernel with one wave per
  * velocity component (default for a Newtonian fluid).
  * tile_w (columns per strip incl. the 8-column halo, one wave per 64; 64,
- * 128 or 256, variant 1 only), seg_h and prefetch (rows loaded ahead, 2 or 3;
- * 2 with 256 lanes and for a power law on a mapped grid) apply to the fused
+ * 128 or 256, variant 1 only), seg_h and prefetch (rows loaded ahead, 2 or 3)
+ * apply to the fused
  * variants; 0 keeps the current value.  With a force field only variants 0
  * and 1 exist, variant 1 with tile_w 64 and prefetch 2 (the default then).  seg_h > 0 cuts every strip into
  * segments of seg_h rows; seg_h = -r (r = 1..4; -1 is the default) selects
@@ -155,7 +155,7 @@ mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_w
 /* Autotuner for this context: times every fused kernel (variant 1 with
  * tile_w 64, 128 and 256, and variant 2 for a Newtonian fluid; only variant 1
  * with tile_w 64 and prefetch 2 under a force field), prefetch
- * depth (2, 3; 2 with 256 lanes) and eight scalings (0.3..3.5) of the
+ * depth (2, 3) and eight scalings (0.3..3.5) of the
  * wall-row cost factors of the one-round balanced partition over `steps`
  * steps of the run itself, times the three fastest again over 4 x `steps`
  * steps, restores the state and step count after each run (the three-pass

@@ -677,8 +677,7 @@ mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t s
     if (variant != 0 && !mdf::fused_shape_ok(c->K, sh))
         return fail(c, MDF_EINVAL,
                     c->K.ff ? "a force field takes tile_w 64 and prefetch 2"
-                            : "tile_w must be 64 or 128 with prefetch 2 or 3, or 256 with prefetch 2 "
-                              "(prefetch 2 only for a power law on a mapped grid)");
+                            : "tile_w must be 64, 128 or 256 and prefetch 2 or 3");
     const int old_variant = c->variant, old_rounds = c->rounds;
     const mdf::FusedShape old_shape = c->shape;
     c->variant = variant;
@@ -761,13 +760,13 @@ mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
     const double scales[8][2] = {{0.3, 0.6}, {0.6, 0.8}, {1.0, 1.0}, {1.35, 1.0},
                                  {1.7, 1.3}, {2.2, 1.6}, {2.8, 2.0}, {3.5, 2.4}};
     std::vector<Cand> cands;
-    const int kernels[4][3] = {{1, 64, 3}, {1, 128, 3}, {1, 256, 2}, {2, 64, 3}};
+    const int kernels[4][3] = {{1, 64, 3}, {1, 128, 3}, {1, 256, 3}, {2, 64, 3}};
     const bool field = c->K.ff != nullptr;
     for (int kv = 0; kv < 4; ++kv) {
         const int var = kernels[kv][0], tw = kernels[kv][1];
         if (var == 2 && (power || field)) continue;
         if (field && tw != 64) continue;
-        const bool pf2_only = field || (power && !c->K.uniform);   // the kernels that exist
+        const bool pf2_only = field;   // the force-field kernels exist for prefetch 2 only
         for (int pf = 2; pf <= (pf2_only ? 2 : kernels[kv][2]); ++pf)
             for (int sc = 0; sc < 8; ++sc) cands.push_back(Cand{var, tw, pf, scales[sc][0], scales[sc][1], 1e30f});
     }

@@ -218,6 +218,38 @@ __device__ __forceinline__ double noneq_shear_sq(const double* phi, const double
     return 2.0 * (mxx * mxx + myy * myy + 2.0 * s12 * s12);
 }
 
+// 1/x for a positive normal x: the hardware reciprocal after two Newton
+// refinements, each of which squares its relative error, so the result is
+// within rounding of 1/x at a third of the cost of an IEEE division.
+__device__ __forceinline__ double rcp_refined(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+// 1/sqrt(x) for a positive normal x: the hardware estimate after two Newton
+// steps y <- y (3/2 - x y^2 / 2), each of which roughly squares the relative
+// error; sqrt(x) from it with one more correction s <- s + y (x - s^2)/2.
+// The general library routines also handle zero, infinities and subnormal
+// arguments with scaling and class tests; the power-law solve never passes
+// those (a zero strain rate takes its own branch), and the refined estimates
+// agree with the correctly rounded values to an ulp or two.
+__device__ __forceinline__ double rsqrt_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    return y * fma(-hx * y, y, 1.5);
+}
+
+__device__ __forceinline__ double sqrt_refined(double x)
+{
+    const double y = rsqrt_refined(x);
+    const double s = x * y;
+    return fma(0.5 * y, fma(-s, s, x), s);
+}
+
 // Local power-law viscosity nu = K (g/(nu + theta))^(n-1), clamped, from the
 // squared strain magnitude q = g^2:
 //  n = 1/2: positive root of nu^2 - b nu - b theta = 0 with b = K^2/g, i.e.
@@ -242,14 +274,14 @@ __device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, 
     double nu;
     if (K.pl == PL_HALF) {
         if (q == 0.0) return K.nu_max;
-        const double b = Kc * Kc * rsqrt(q);
-        nu = 0.5 * (b + sqrt(b * (b + 4.0 * theta)));
+        const double b = Kc * Kc * rsqrt_refined(q);
+        nu = 0.5 * (b + sqrt_refined(b * (b + 4.0 * theta)));
     } else {
         if (q == 0.0) return K.nu_min;
-        const double r = Kc * Kc * sqrt(q);
+        const double r = Kc * Kc * sqrt_refined(q);
         const unsigned long long rb = static_cast<unsigned long long>(__double_as_longlong(r));
         const double cb = __longlong_as_double(static_cast<long long>(rb / 3ull + (682ull << 52)));
-        double x = fmin(cb, sqrt(r * (1.0 / theta)));
+        double x = fmin(cb, sqrt_refined(r * (1.0 / theta)));
 #pragma unroll
         for (int it = 0; it < 3; ++it) {
             const double f = x * x * (x + theta) - r;
@@ -263,16 +295,6 @@ __device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, 
         nu = x;
     }
     return fmin(fmax(nu, K.nu_min), K.nu_max);
-}
-
-// 1/x for a positive normal x: the hardware reciprocal after two Newton
-// refinements, each of which squares its relative error, so the result is
-// within rounding of 1/x at a third of the cost of an IEEE division.
-__device__ __forceinline__ double rcp_refined(double x)
-{
-    double y = __builtin_amdgcn_rcp(x);
-    y = fma(y, fma(-x, y, 1.0), y);
-    return fma(y, fma(-x, y, 1.0), y);
 }
 
 // Relaxation factors at a local viscosity nu, with s = c_s^2/nu and

@@ -21,10 +21,7 @@ MDF_FAMILY_DECL(256, true)
 bool fused_shape_ok(const StepConsts& K, FusedShape sh)
 {
     if (K.ff) return sh.tile_w == 64 && sh.prefetch == 2;   // force-field kernels: 64 lanes, prefetch 2
-    // a power law on a mapped grid has prefetch-2 kernels only (a third row would spill)
-    if (K.pl != PL_NEWTON && !K.uniform && sh.prefetch != 2) return false;
-    return ((sh.tile_w == 64 || sh.tile_w == 128) && sh.prefetch >= 2 && sh.prefetch <= 3) ||
-           (sh.tile_w == 256 && sh.prefetch == 2);
+    return (sh.tile_w == 64 || sh.tile_w == 128 || sh.tile_w == 256) && sh.prefetch >= 2 && sh.prefetch <= 3;
 }
 
 hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int tile_w,

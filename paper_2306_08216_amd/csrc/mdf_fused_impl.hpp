@@ -562,7 +562,9 @@ hipError_t launch_tw(const StepConsts& K, const FusedGrid& G, const double* fin,
 }  // namespace fusedk
 
 // Every k_fused instantiation of one tile width and fluid model, chosen by
-// prefetch depth, grid mapping and force field.  Each (TW, PLW) pair is
+// prefetch depth (2 or 3 rows; a force field takes 2), grid mapping and force
+// field.  The deepest instantiation (256 lanes, power law, mapped grid, both
+// walls, prefetch 3) holds 256 VGPRs and 234 AGPRs, no scratch.  Each (TW, PLW) pair is
 // instantiated in a translation unit of its own (mdf_fused_w*.hip) so that
 // the six compile in parallel.
 template <int TW, bool PLW>
@@ -577,12 +579,9 @@ hipError_t launch_fused_family(const StepConsts& K, const fusedk::FusedGrid& G, 
         }
     }
     if (K.ff) return hipErrorInvalidValue;
-    if constexpr (TW <= 128) {
-        // prefetch 3 (power law on a mapped grid: a third row would spill registers)
-        if (prefetch >= 3 && (!PLW || K.uniform)) {
-            if (K.uniform) return launch_tw<TW, PLW, 3, true, false>(K, G, fin, fout, s);
-            if constexpr (!PLW) return launch_tw<TW, PLW, 3, false, false>(K, G, fin, fout, s);
-        }
+    if (prefetch >= 3) {
+        if (K.uniform) return launch_tw<TW, PLW, 3, true, false>(K, G, fin, fout, s);
+        return launch_tw<TW, PLW, 3, false, false>(K, G, fin, fout, s);
     }
     if (K.uniform) return launch_tw<TW, PLW, 2, true, false>(K, G, fin, fout, s);
     return launch_tw<TW, PLW, 2, false, false>(K, G, fin, fout, s);
