@@ -253,8 +253,8 @@ def main():
     ap.add_argument("--variant", type=int, default=-1,
                     help="step kernel: 0 three-pass, 1 fused one wave per strip, 2 fused one wave per "
                          "velocity component (-1: the tuning cache's choice)")
-    ap.add_argument("--cpu-serial-steps", type=int, default=1, help="oracle steps on one thread (0 = skip baseline)")
-    ap.add_argument("--cpu-omp-steps", type=int, default=2, help="oracle steps per run on all cores")
+    ap.add_argument("--cpu-serial-steps", type=int, default=2, help="oracle steps on one thread (0 = skip baseline)")
+    ap.add_argument("--cpu-omp-steps", type=int, default=4, help="oracle steps per run on all cores")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary lines (1024^2 cavity, 256-instance batch)")
     ap.add_argument("--tuning", default=TUNING,
