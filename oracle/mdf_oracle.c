@@ -461,6 +461,12 @@ static void one_step(orc_state* st)
     int nx = st->nx, ny = st->ny;
     long n = (long)st->n;
     const double* Fa[2] = {st->Fx, st->Fy};
+    /* time factor of the force at t = steps dt and its time derivative: F(x, t)
+     * = F(x) m(t), d_t F = F(x) m'(t); m = 1, m' = 0 for a steady force */
+    const double tn = (double)st->steps * st->dt;
+    const int harmonic = st->p.force_harmonic != 0;
+    const double m = harmonic ? cos(st->p.force_omega * tn + st->p.force_phase) : 1.0;
+    const double dm = harmonic ? -st->p.force_omega * sin(st->p.force_omega * tn + st->p.force_phase) : 0.0;
 
     /* Step (1): f_hat^+ and f_bar^+ at every node. */
 #pragma omp parallel for schedule(static)
@@ -473,9 +479,9 @@ static void one_step(orc_state* st)
     }
     orc_wall_update(st, st->fbar_plus);
 
-    /* Step (2): f_bar(t+h) = f_bar^+ - h c_j . grad f_bar^+ + h w_j F_alpha
-     * (eq. 2.2.11 with the O(h^2) and G terms dropped per Remark 2, eq. 2.2.6;
-     * the force is steady, so its time derivative vanishes). */
+    /* Step (2): f_bar(t+h) = f_bar^+ - h c_j . grad f_bar^+ + h w_j F_alpha(t)
+     * (eq. 2.3.25: eq. 2.2.11 with the G terms and the h^2/2 d_t F term dropped
+     * per Remark 2; F_j = w_j F of eq. 2.2.6). */
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -485,7 +491,7 @@ static void one_step(orc_state* st)
                 for (int j = 0; j < NQ; ++j) {
                     const double* pl = st->fbar_plus + (size_t)(a * NQ + j) * n;
                     st->fbar[(size_t)(a * NQ + j) * n + i] =
-                        pl[i] - st->h * cdotgrad(st, pl, x, y, j) + st->h * WJ[j] * Fa[a][i];
+                        pl[i] - st->h * cdotgrad(st, pl, x, y, j) + st->h * WJ[j] * Fa[a][i] * m;
                 }
         }
 
@@ -502,8 +508,9 @@ static void one_step(orc_state* st)
         }
     orc_wall_update(st, st->fmid);
 
-    /* Step (4): f_hat(t+dt) = f_hat^+ - dt c_j . grad f(t+h) + dt w_j F_alpha
-     * (eq. 2.3.24; the dt^2/2 d_t F term vanishes for a steady force). */
+    /* Step (4): f_hat(t+dt) = f_hat^+ - dt c_j . grad f(t+h) + dt w_j F_alpha(t)
+     * + (dt^2/2) w_j d_t F_alpha(t)  (eq. 2.3.24; the last term vanishes for a
+     * steady force). */
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -514,7 +521,8 @@ static void one_step(orc_state* st)
                     size_t k = (size_t)(a * NQ + j) * n;
                     st->fnew[k + i] = st->fhat_plus[k + i]
                                     - st->dt * cdotgrad(st, st->fmid + k, x, y, j)
-                                    + st->dt * WJ[j] * Fa[a][i];
+                                    + st->dt * WJ[j] * Fa[a][i] * m
+                                    + 0.5 * st->dt * st->dt * WJ[j] * Fa[a][i] * dm;
                 }
         }
     orc_wall_update(st, st->fnew);
@@ -553,6 +561,9 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     if (!(p->nu > 0.0)) return NULL;
     if (p->pl_n != 1.0 && !(p->nu_min > 0.0 && p->nu_max >= p->nu_min)) return NULL;
     if ((p->inv_dx_x || p->inv_dx_y) && !(p->dx_min > 0.0)) return NULL;
+    if (p->force_harmonic != 0 &&
+        (p->force_harmonic != 1 || !isfinite(p->force_omega) || !isfinite(p->force_phase)))
+        return NULL;
 
     orc_state* st = (orc_state*)calloc(1, sizeof(orc_state));
     st->p = *p;

@@ -39,8 +39,12 @@ typedef struct {
     const double* inv_dx_x;  /* nx entries: d(xi)/dx / d(xi), i.e. 1/(X'(xi_i) dxi); NULL = uniform */
     const double* inv_dx_y;  /* ny entries, same meaning for y                        */
     double  dx_min;          /* smallest node spacing; used for dt when metrics are given */
-    const double* force_x;   /* ny*nx entries added to fx at each node (steady F(x), eq. 2.2.6); NULL = none */
+    const double* force_x;   /* ny*nx entries added to fx at each node (F(x), eq. 2.2.6); NULL = none */
     const double* force_y;   /* same for fy                                           */
+    /* time dependence of the force: 0 = steady; 1 = F(x, t) = F(x) cos(force_omega t + force_phase),
+     * with F(x) the uniform part plus the field above, t = steps * dt */
+    double  force_omega, force_phase;
+    int32_t force_harmonic;
 } orc_params;
 
 typedef struct orc_state orc_state;

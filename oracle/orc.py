@@ -32,6 +32,7 @@ class OrcParams(C.Structure):
         ("inv_dx_x", _dp), ("inv_dx_y", _dp),
         ("dx_min", C.c_double),
         ("force_x", _dp), ("force_y", _dp),
+        ("force_omega", C.c_double), ("force_phase", C.c_double), ("force_harmonic", C.c_int32),
     ]
 
 
@@ -121,7 +122,8 @@ def _params(prob):
     keep += [gx, gy, ffx, ffy]
     p = OrcParams(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                   prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
-                  prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min, _ptr(ffx), _ptr(ffy))
+                  prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min, _ptr(ffx), _ptr(ffy),
+                  prob.force_omega, prob.force_phase, 1 if prob.force_harmonic else 0)
     return p, keep
 
 

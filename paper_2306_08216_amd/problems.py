@@ -53,8 +53,11 @@ class Problem:
     inv_dx_x: Optional[np.ndarray] = None
     inv_dx_y: Optional[np.ndarray] = None
     dx_min: float = 0.0
-    force_x: Optional[np.ndarray] = None   # (ny, nx) steady force field added to fx (None: none)
+    force_x: Optional[np.ndarray] = None   # (ny, nx) force field added to fx (None: none)
     force_y: Optional[np.ndarray] = None   # (ny, nx) added to fy
+    force_harmonic: bool = False           # F(x, t) = F(x) cos(force_omega t + force_phase) (else steady)
+    force_omega: float = 0.0
+    force_phase: float = 0.0
     name: str = ""
 
     @property
@@ -134,6 +137,58 @@ def four_roll_mill_exact(prob: Problem, u0: float = 1e-4):
     c, ss = u0 * np.cos(X) * np.cos(Y), u0 * np.sin(X) * np.sin(Y)
     return {"u": u0 * np.sin(X) * np.cos(Y), "v": -u0 * np.sin(Y) * np.cos(X), "ux": c, "uy": -ss,
             "vx": ss, "vy": -c, "Sxx": c, "Sxy": 0.0 * c, "Syy": -c, "omega": 2.0 * ss, "Omega_xy": -ss}
+
+
+def swept_vortex(n: int = 32, u0: float = 0.01, nu: float = 0.01, f0: float = 1e-3, omega: float = 0.2,
+                 phase: float = 0.0, cfl: float = 0.5, eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+    """Taylor-Green vortex (Sec. 4.1 setup) on the periodic [0, 2pi]^2 swept by a
+    spatially uniform stream that an oscillating force F = (f0 cos(omega t +
+    phase), 0) drives from rest.  By Galilean invariance the solution is the
+    decaying vortex carried by the stream (swept_vortex_exact)."""
+    prob = taylor_green(n, u0=u0, nu=nu, cfl=cfl, eta=eta, s_ratio=s_ratio)
+    prob.fx = f0
+    prob.force_harmonic, prob.force_omega, prob.force_phase = True, omega, phase
+    prob.name = f"swept_vortex_{n}"
+    return prob
+
+
+def swept_vortex_exact(prob: Problem, t: float, u0: float = 0.01, f0: float = 1e-3):
+    """u, v, P of swept_vortex at time t: the stream U(t) = (f0/omega)(sin(omega t
+    + phase) - sin phase), its displacement X(t) = integral of U, and the
+    vortex u0 e^{-2 nu t} (sin(x - X) cos y, -cos(x - X) sin y) with pressure
+    (u0^2 e^{-4 nu t}/4)(cos 2(x - X) + cos 2y)."""
+    w, ph = prob.force_omega, prob.force_phase
+    U = f0 / w * (math.sin(w * t + ph) - math.sin(ph))
+    Xs = f0 / w * ((math.cos(ph) - math.cos(w * t + ph)) / w - t * math.sin(ph))
+    X, Y = np.meshgrid(prob.node_x(), prob.node_y(), indexing="xy")
+    d = u0 * math.exp(-2.0 * prob.nu * t)
+    u = U + d * np.sin(X - Xs) * np.cos(Y)
+    v = -d * np.cos(X - Xs) * np.sin(Y)
+    p = 0.25 * d * d * (np.cos(2.0 * (X - Xs)) + np.cos(2.0 * Y))
+    return {"u": u, "v": v, "p": p, "U": U}
+
+
+def pulsed_vortex(n: int = 32, a0: float = 0.0, nu: float = 0.01, f0: float = 1e-3, omega: float = 0.2,
+                  cfl: float = 0.5, eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+    """Cellular flow on the periodic [0, 2pi]^2 driven by the force field
+    F(x, t) = f0 cos(omega t) (sin x cos y, -cos x sin y): the velocity stays in
+    that mode, u = a(t) (sin x cos y, -cos x sin y), with a' = -2 nu a + f0 cos(omega t)
+    (its advection is a pressure gradient), started at amplitude a0."""
+    L = 2.0 * math.pi
+    x = _axis_nodes(n, L, PERIODIC)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    sx, sy = np.sin(X) * np.cos(Y), -np.cos(X) * np.sin(Y)
+    p = 0.25 * a0 * a0 * (np.cos(2.0 * X) + np.cos(2.0 * Y))
+    return Problem(nx=n, ny=n, lx=L, ly=L, nu=nu, u0=a0 * sx, v0=a0 * sy, p0=p, cfl=cfl, eta=eta,
+                   s_ratio=s_ratio, force_x=f0 * sx, force_y=f0 * sy, force_harmonic=True, force_omega=omega,
+                   name=f"pulsed_vortex_{n}")
+
+
+def pulsed_vortex_amplitude(prob: Problem, t: float, a0: float = 0.0, f0: float = 1e-3) -> float:
+    """a(t) of pulsed_vortex: the solution of a' + 2 nu a = f0 cos(omega t), a(0) = a0."""
+    k, w = 2.0 * prob.nu, prob.force_omega
+    den = k * k + w * w
+    return f0 * (k * math.cos(w * t) + w * math.sin(w * t)) / den + (a0 - f0 * k / den) * math.exp(-k * t)
 
 
 def periodic_flow(nx: int = 32, ny: Optional[int] = None, u0: float = 0.1, nu: float = 0.01, cfl: float = 0.5,

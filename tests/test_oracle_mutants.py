@@ -67,11 +67,23 @@ CASES = [
      "out[k] = few[k] + 2.0 * (ph1[k] - fe1[k]) - (ph2[k] - fe2[k]);", "out[k] = few[k] + (ph1[k] - fe1[k]);",
      "test_oracle_flows", "test_poiseuille_against_closed_form_and_table2"),
     ("half step without the force",
-     "+ st->h * WJ[j] * Fa[a][i];", ";",
+     "+ st->h * WJ[j] * Fa[a][i] * m;", ";",
      "test_oracle_flows", "test_half_step_carries_the_force"),
     ("full step with h instead of dt on the force",
-     "+ st->dt * WJ[j] * Fa[a][i];", "+ st->h * WJ[j] * Fa[a][i];",
+     "+ st->dt * WJ[j] * Fa[a][i] * m", "+ st->h * WJ[j] * Fa[a][i] * m",
      "test_oracle_forced", "test_four_roll_mill_steady_solution"),
+    ("full step without the (dt^2/2) d_t F term of eq. 2.3.24",
+     "+ 0.5 * st->dt * st->dt * WJ[j] * Fa[a][i] * dm;", ";",
+     "test_oracle_forced", "test_harmonic_force_mean_momentum"),
+    ("d_t F with the wrong sign",
+     "const double dm = harmonic ? -st->p.force_omega", "const double dm = harmonic ? st->p.force_omega",
+     "test_oracle_forced", "test_harmonic_force_mean_momentum"),
+    ("force taken one step late",
+     "const double tn = (double)st->steps * st->dt;", "const double tn = (double)(st->steps + 1) * st->dt;",
+     "test_oracle_forced", "test_harmonic_force_mean_momentum"),
+    ("half step with the force not modulated in time",
+     "+ st->h * WJ[j] * Fa[a][i] * m;", "+ st->h * WJ[j] * Fa[a][i];",
+     "test_oracle_forced", "test_pulsed_vortex_amplitude"),
     ("force field of the x equation read for both",
      "st->Fy[i] = p->fy + (p->force_y ? p->force_y[i] : 0.0);",
      "st->Fy[i] = p->fy + (p->force_x ? p->force_x[i] : 0.0);",
