@@ -69,6 +69,13 @@ typedef struct {
     const double* force_x;   /* HOST, ny*nx values (x fastest) added to fx at each node: a steady body
                                 force field F(x) (eq. 2.2.6, Secs. 4.1-4.2), or NULL (none)          */
     const double* force_y;   /* HOST, ny*nx values added to fy, or NULL                            */
+    /* Time dependence of the body force.  0: steady.  1: F(x, t) = F(x) cos(force_omega t +
+     * force_phase), F(x) the uniform part plus the field above, t = (steps taken) * dt; the
+     * full step then carries the (dt^2/2) d_t F term of eq. 2.3.24 and the half step h F(t)
+     * (eq. 2.3.25).  force_omega and force_phase must be finite.  Batches take only 0. */
+    double  force_omega;     /* angular frequency of the force (time units of nu and dt)          */
+    double  force_phase;     /* phase at t = 0                                                      */
+    int32_t force_harmonic;  /* 0 or 1                                                              */
 } mdf_params;
 
 /* Bytes of device workspace a context for these parameters needs, or 0 if the

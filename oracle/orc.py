@@ -123,7 +123,7 @@ def _params(prob):
     p = OrcParams(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                   prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
                   prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min, _ptr(ffx), _ptr(ffy),
-                  prob.force_omega, prob.force_phase, 1 if prob.force_harmonic else 0)
+                  prob.force_omega, prob.force_phase, int(prob.force_harmonic))
     return p, keep
 
 

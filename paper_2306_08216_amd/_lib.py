@@ -32,6 +32,7 @@ class mdf_params(C.Structure):
         ("inv_dx_x", _dp), ("inv_dx_y", _dp),
         ("dx_min", C.c_double),
         ("force_x", _dp), ("force_y", _dp),
+        ("force_omega", C.c_double), ("force_phase", C.c_double), ("force_harmonic", C.c_int32),
     ]
 
 

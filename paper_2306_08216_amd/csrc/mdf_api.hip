@@ -113,7 +113,29 @@ const char* validate(const mdf_params* p)
     if (p->pl_n != 1.0 && !(p->nu_min > 0.0 && p->nu_max >= p->nu_min)) return "power law needs 0 < nu_min <= nu_max";
     if ((p->inv_dx_x || p->inv_dx_y) && !(p->dx_min > 0.0)) return "metric arrays need dx_min > 0";
     if (!std::isfinite(p->fx) || !std::isfinite(p->fy) || !std::isfinite(p->lid_u)) return "non-finite force or lid speed";
+    if (p->force_harmonic != 0 && p->force_harmonic != 1) return "force_harmonic must be 0 or 1";
+    if (p->force_harmonic && !(std::isfinite(p->force_omega) && std::isfinite(p->force_phase)))
+        return "non-finite force_omega or force_phase";
     return nullptr;
+}
+
+// Force terms of the step that starts at time t = step * dt for a force
+// F(x) cos(omega t + phase): the half step adds h w F(t) (eq. 2.3.25), the full
+// step dt w F(t) + (dt^2/2) w d_t F(t) (eq. 2.3.24).  The kernels read them as
+// the scalars h w F_alpha and dt w F_alpha of the uniform force, and h w and
+// dt w that multiply a force field node by node.
+void set_force_time(StepConsts& K, const mdf_params& p, int64_t step)
+{
+    const double t = (double)step * K.dt;
+    const double m = std::cos(p.force_omega * t + p.force_phase);
+    const double dm = -p.force_omega * std::sin(p.force_omega * t + p.force_phase);
+    const double F[2] = {p.fx, p.fy};
+    for (int a = 0; a < 2; ++a) {
+        K.hwf[a] = K.h * K.w * F[a] * m;
+        K.dwf[a] = K.dt * K.w * F[a] * m + 0.5 * K.dt * K.dt * K.w * F[a] * dm;
+    }
+    K.hw = K.h * K.w * m;
+    K.dw = K.dt * K.w * m + 0.5 * K.dt * K.dt * K.w * dm;
 }
 
 // Constants of the method for one run (Sec. 2.2; eq. 3.1 for dt).
@@ -365,6 +387,7 @@ const char* validate_batch(const mdf_params* ps, int count)
             return "batched instances must be periodic on both axes";
         if (ps[i].inv_dx_x || ps[i].inv_dx_y) return "batched instances must use uniform grids";
         if (has_force_field(&ps[i])) return "batched instances take a uniform force only";
+        if (ps[i].force_harmonic) return "batched instances take a steady force only";
         if (ps[i].pl_n != ps[0].pl_n) return "batched instances must share the fluid model (pl_n)";
     }
     return nullptr;
@@ -600,6 +623,7 @@ mdf_status mdf_step(mdf_ctx* c, int64_t n)
     for (int64_t i = 0; i < n; ++i) {
         const double* fin = c->f[c->cur];
         double* fout = c->f[1 - c->cur];
+        if (c->p.force_harmonic) set_force_time(c->K, c->p, c->steps);
         hipError_t e;
         if (c->variant == 0)
             e = mdf::launch_three_pass(c->K, fin, c->fbp, c->fmid, fout, c->stream);

@@ -36,7 +36,8 @@ def params_of(prob: Problem, keep: list) -> L.mdf_params:
     return L.mdf_params(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                         prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
                         prob.fx, prob.fy, arr(prob.inv_dx_x), arr(prob.inv_dx_y), prob.dx_min,
-                        arr(prob.force_x), arr(prob.force_y))
+                        arr(prob.force_x), arr(prob.force_y), prob.force_omega, prob.force_phase,
+                        int(prob.force_harmonic))
 
 
 class Solver:

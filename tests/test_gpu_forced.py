@@ -1,6 +1,8 @@
-"""GPU parity of the steady force field F(x) (eq. 2.2.6; the four-roll mill of
-Sec. 4.1 and the periodic flow of Sec. 4.2, and forced walled and power-law
-flows) through the C ABI against the oracle, element by element, to 1e-12."""
+"""GPU parity of body forces through the C ABI against the oracle, element by
+element, to 1e-12: the steady force field F(x) (eq. 2.2.6; the four-roll mill
+of Sec. 4.1, the periodic flow of Sec. 4.2, forced walled and power-law flows)
+and forces with harmonic time dependence, whose full step carries the
+(dt^2/2) d_t F term of eq. 2.3.24."""
 import functools
 import math
 import sys
@@ -52,6 +54,22 @@ def _forced_cavity(n=48):
     return prob
 
 
+def _oscillating_channel(n=32, pl_n=1.0):
+    """Channel (walls in y) driven by a uniform force oscillating in time
+    (Womersley-type flow), Newtonian or power law."""
+    prob = P.poiseuille(n, nu=0.01, force=2e-4) if pl_n == 1.0 else \
+        P.poiseuille(n, nu=5e-4, force=2e-4, pl_n=pl_n, nu_min=1e-5, nu_max=0.05)
+    prob.force_harmonic, prob.force_omega, prob.force_phase = True, 0.7, 0.4
+    return prob
+
+
+def _pulsed_cavity(n=40):
+    """Lid-driven cavity with a harmonic force field on top of the lid."""
+    prob = _forced_cavity(n)
+    prob.force_harmonic, prob.force_omega, prob.force_phase = True, 0.3, -0.2
+    return prob
+
+
 def _periodic_mapped():
     pos, g, dxm = P.sine_mapping(64, 0.2, 1.0)
     return P.periodic_flow(64, 32, nu=0.005, inv_dx_x=g, x_nodes=pos, dx_min=dxm)
@@ -66,13 +84,22 @@ CASES = {
     "channel_pl0.5": lambda: (_forced_channel(24, 0.5), 300),
     "channel_pl1.5": lambda: (_forced_channel(24, 1.5), 300),
     "cavity48": lambda: (_forced_cavity(48), 300),
+    "pulsed_vortex48": lambda: (P.pulsed_vortex(48, a0=0.01, omega=0.4), 400),
+    "pulsed_cavity40": lambda: (_pulsed_cavity(40), 300),
+}
+
+# uniform forces with harmonic time dependence: every kernel variant takes them
+UNIFORM_HARMONIC = {
+    "swept_vortex40": lambda: (P.swept_vortex(40, f0=2e-3, omega=0.3, phase=0.5), 400),
+    "oscillating_channel32": lambda: (_oscillating_channel(32), 400),
+    "oscillating_channel_pl1.5": lambda: (_oscillating_channel(24, 1.5), 300),
 }
 
 
 @functools.lru_cache(maxsize=None)
 def oracle_run(key):
     from oracle.orc import Oracle
-    prob, steps = CASES[key]()
+    prob, steps = {**CASES, **UNIFORM_HARMONIC}[key]()
     o = Oracle(prob)
     o.step(steps)
     return o, prob, steps
@@ -133,3 +160,37 @@ def test_force_field_derived_quantities(gpu):
     for k in range(13):
         scale = 2 * prob.nu if k in (8, 9, 10) else 1.0
         assert np.abs(d[k] - do[k]).max() <= bound * scale + 1e-18, k
+
+
+@pytest.mark.parametrize("key", sorted(UNIFORM_HARMONIC))
+@pytest.mark.parametrize("variant,shape", [(0, (0, 0)), (1, (64, -1, 2)), (1, (256, -1, 3)), (1, (64, 7, 2)),
+                                           (2, (64, -1, 2))])
+def test_harmonic_uniform_force_parity(gpu, key, variant, shape):
+    """F(t) = F cos(omega t + phase) on every kernel variant and strip shape,
+    with the step's time taken from the run's own step count."""
+    o, prob, steps = oracle_run(key)
+    say(f"[gpu forced] harmonic case={key} nx={prob.nx} ny={prob.ny} steps={steps} variant={variant} shape={shape}")
+    s = gpu(prob, device="cuda:0")
+    s.set_kernel(variant, *shape)
+    s.step(steps // 3)            # several calls: the force's time runs on across them
+    s.step(steps - steps // 3)
+    f = s.save().cpu().numpy()
+    s.close()
+    err = np.abs(f - o.f()).max()
+    say(f"    max|df|={err:.3e} max|f|={np.abs(o.f()).max():.3e}")
+    assert np.all(np.isfinite(f))
+    assert err <= TOL, (key, err)
+
+
+def test_harmonic_force_time_survives_autotune(gpu):
+    """The autotuner times candidates on the run itself and restores its state
+    and step count, so the force's phase after tuning is the untuned one."""
+    o, prob, steps = oracle_run("swept_vortex40")
+    s = gpu(prob, device="cuda:0")
+    s.autotune(3)
+    assert s.steps == 0
+    s.step(steps)
+    err = np.abs(s.save().cpu().numpy() - o.f()).max()
+    s.close()
+    say(f"[gpu forced] harmonic after autotune: max|df|={err:.3e}")
+    assert err <= TOL
