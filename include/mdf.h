@@ -300,7 +300,7 @@ mdf_status mdf_batch_step_graph(mdf_batch* b, int64_t n);
 
 /* Kernel for the batch: variant 1 (one wave per strip; tile_w 64, 128 or 256
  * lanes per strip, one wave per 64) or 2 (one wave per velocity component;
- * tile_w 64), tile_w 0 meaning 64; prefetch 2 or 3 rows (2 with 256 lanes);
+ * tile_w 64), tile_w 0 meaning 64; prefetch 2 or 3 rows;
  * `rounds` (1..8) rounds of waves in the balanced partition.  Other values
  * are MDF_EINVAL.  Rebuilds the plan (synchronous). */
 mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t tile_w, int32_t prefetch, int32_t rounds);

@@ -359,6 +359,7 @@ struct mdf_batch {
     int table_cap = 0;
     std::vector<mdf::BatchInst> insts;
     bool powerlaw = false;
+    int pl = mdf::PL_NEWTON;      // viscosity law every instance shares
     int variant = 2, tile_w = 64, prefetch = 2, rounds = 1, slots = 1024, nwg = 0;
     int cur = 0;
     int64_t steps = 0;
@@ -466,7 +467,7 @@ mdf_status batch_plan(mdf_batch* b)
 hipError_t batch_launch(mdf_batch* b, const double* fin, double* fout, hipStream_t s)
 {
     if (b->variant == 1)
-        return mdf::launch_fused_batch(b->d_insts, b->d_table, b->nwg, b->powerlaw, b->tile_w, b->prefetch, fin, fout,
+        return mdf::launch_fused_batch(b->d_insts, b->d_table, b->nwg, b->pl, b->tile_w, b->prefetch, fin, fout,
                                        s);
     return mdf::launch_fused2_batch(b->d_insts, b->d_table, b->nwg, b->powerlaw, b->prefetch, fin, fout, s);
 }
@@ -1045,6 +1046,7 @@ mdf_status mdf_batch_init(const mdf_params* ps, int32_t count, const double* con
     b->diag_out = (double*)(b->ws + B.off_do);
     b->state_doubles = B.state_doubles;
     b->powerlaw = ps[0].pl_n != 1.0;
+    b->pl = ps[0].pl_n == 1.0 ? mdf::PL_NEWTON : (ps[0].pl_n == 0.5 ? mdf::PL_HALF : mdf::PL_THREE_HALVES);
     b->variant = b->powerlaw ? 1 : 2;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1148,7 +1150,6 @@ mdf_status mdf_batch_set_kernel(mdf_batch* b, int32_t variant, int32_t tile_w, i
     if (tile_w != 64 && (variant == 2 || (tile_w != 128 && tile_w != 256)))
         return bfail(b, MDF_EINVAL, "tile_w must be 64, 128 or 256 (variant 1) or 64 (variant 2)");
     if (prefetch != 2 && prefetch != 3) return bfail(b, MDF_EINVAL, "prefetch must be 2 or 3");
-    if (tile_w == 256 && prefetch != 2) return bfail(b, MDF_EINVAL, "256-lane strips take prefetch 2");
     if (rounds < 1 || rounds > 8) return bfail(b, MDF_EINVAL, "rounds must lie in 1..8");
     const int ov = b->variant, ot = b->tile_w, op = b->prefetch, orr = b->rounds;
     b->variant = variant;
@@ -1184,7 +1185,8 @@ mdf_status mdf_batch_autotune(mdf_batch* b, int32_t steps, int32_t* choice)
         float ms;
     };
     std::vector<Cand> cands;
-    const int kernels[7][3] = {{2, 64, 2}, {2, 64, 3}, {1, 64, 2}, {1, 64, 3}, {1, 128, 2}, {1, 128, 3}, {1, 256, 2}};
+    const int kernels[8][3] = {{2, 64, 2}, {2, 64, 3}, {1, 64, 2}, {1, 64, 3}, {1, 128, 2}, {1, 128, 3}, {1, 256, 2},
+                               {1, 256, 3}};
     for (int r = 1; r <= 3; ++r)
         for (const auto& k : kernels)
             if (!(k[0] == 2 && b->powerlaw)) cands.push_back(Cand{k[0], k[1], k[2], r, 1e30f});

@@ -268,16 +268,21 @@ __device__ __forceinline__ double sqrt_refined(double x)
 //           perturbs the correction itself; the last correction is below 1e-6
 //           of the root.  A root beyond the clamp range is clamped like the
 //           n = 1/2 one.
-__device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, double theta)
+template <int PL>
+__device__ __forceinline__ double powerlaw_nu_sq_t(const StepConsts& K, double q, double theta)
 {
     const double Kc = K.nu;
+    // A node at rest (q = 0) takes the clamp bound its index gives; it runs the
+    // same instructions on a stand-in q = 1 and selects, so that no lane
+    // branches and the collisions around stay one basic block.
+    const bool rest = q == 0.0;
+    q = rest ? 1.0 : q;
     double nu;
-    if (K.pl == PL_HALF) {
-        if (q == 0.0) return K.nu_max;
+    if constexpr (PL == PL_HALF) {
         const double b = Kc * Kc * rsqrt_refined(q);
         nu = 0.5 * (b + sqrt_refined(b * (b + 4.0 * theta)));
+        nu = rest ? K.nu_max : nu;
     } else {
-        if (q == 0.0) return K.nu_min;
         const double r = Kc * Kc * sqrt_refined(q);
         const unsigned long long rb = static_cast<unsigned long long>(__double_as_longlong(r));
         const double cb = __longlong_as_double(static_cast<long long>(rb / 3ull + (682ull << 52)));
@@ -292,9 +297,16 @@ __device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, 
             y = fma(y, fma(-den, y, 1.0), y);
             x -= 2.0 * f * d1 * y;
         }
-        nu = x;
+        nu = rest ? K.nu_min : x;
     }
     return fmin(fmax(nu, K.nu_min), K.nu_max);
+}
+
+// The same with the index read from the constants at run time.
+__device__ __forceinline__ double powerlaw_nu_sq(const StepConsts& K, double q, double theta)
+{
+    if (K.pl == PL_HALF) return powerlaw_nu_sq_t<PL_HALF>(K, q, theta);
+    return powerlaw_nu_sq_t<PL_THREE_HALVES>(K, q, theta);
 }
 
 // Relaxation factors at a local viscosity nu, with s = c_s^2/nu and
@@ -327,7 +339,7 @@ __device__ __forceinline__ void step1_factors_t(const StepConsts& K, const doubl
         rb = Relax{K.b_s, K.b_p};
         return;
     }
-    relax_ab_nu(K, powerlaw_nu_sq(K, noneq_shear_sq(fh, fe, K.c), K.theta1), ra, rb);
+    relax_ab_nu(K, powerlaw_nu_sq_t<PL>(K, noneq_shear_sq(fh, fe, K.c), K.theta1), ra, rb);
 }
 
 // Step (3) factors q(s), q(s') for the collision of f_bar.
@@ -335,7 +347,7 @@ template <int PL>
 __device__ __forceinline__ Relax step3_factors_t(const StepConsts& K, const double* fb, const double* fe)
 {
     if (PL == PL_NEWTON) return Relax{K.q_s, K.q_p};
-    return relax_q_nu(K, powerlaw_nu_sq(K, noneq_shear_sq(fb, fe, K.c), K.theta3));
+    return relax_q_nu(K, powerlaw_nu_sq_t<PL>(K, noneq_shear_sq(fb, fe, K.c), K.theta3));
 }
 
 __device__ __forceinline__ void step1_factors(const StepConsts& K, const double* fh, const double* fe, Relax& ra,
@@ -343,14 +355,17 @@ __device__ __forceinline__ void step1_factors(const StepConsts& K, const double*
 {
     if (K.pl == PL_NEWTON)
         step1_factors_t<PL_NEWTON>(K, fh, fe, ra, rb);
+    else if (K.pl == PL_HALF)
+        step1_factors_t<PL_HALF>(K, fh, fe, ra, rb);
     else
-        step1_factors_t<PL_HALF>(K, fh, fe, ra, rb);   // both power-law indices share the code path
+        step1_factors_t<PL_THREE_HALVES>(K, fh, fe, ra, rb);
 }
 
 __device__ __forceinline__ Relax step3_factors(const StepConsts& K, const double* fb, const double* fe)
 {
     if (K.pl == PL_NEWTON) return step3_factors_t<PL_NEWTON>(K, fb, fe);
-    return step3_factors_t<PL_HALF>(K, fb, fe);
+    if (K.pl == PL_HALF) return step3_factors_t<PL_HALF>(K, fb, fe);
+    return step3_factors_t<PL_THREE_HALVES>(K, fb, fe);
 }
 
 // Step (1): f_hat -> f_hat^+ (eq. 2.2.14) and f_bar^+ (eq. 2.2.15).

@@ -8,8 +8,8 @@ namespace mdf {
 #define MDF_FAMILY_DECL(TW, PLW)                                                                                     \
     extern template hipError_t launch_fused_family<TW, PLW>(const StepConsts&, const fusedk::FusedGrid&, int,          \
                                                             const double*, double*, hipStream_t);                    \
-    extern template hipError_t launch_batch_family<TW, PLW>(const BatchInst*, const int4*, int, int, const double*,     \
-                                                            double*, hipStream_t);
+    extern template hipError_t launch_batch_family<TW, PLW>(const BatchInst*, const int4*, int, int, int,              \
+                                                            const double*, double*, hipStream_t);
 MDF_FAMILY_DECL(64, false)
 MDF_FAMILY_DECL(64, true)
 MDF_FAMILY_DECL(128, false)
@@ -24,20 +24,21 @@ bool fused_shape_ok(const StepConsts& K, FusedShape sh)
     return (sh.tile_w == 64 || sh.tile_w == 128 || sh.tile_w == 256) && sh.prefetch >= 2 && sh.prefetch <= 3;
 }
 
-hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int tile_w,
-                              int prefetch, const double* fin, double* fout, hipStream_t s)
+hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, int pl, int tile_w, int prefetch,
+                              const double* fin, double* fout, hipStream_t s)
 {
     if (nwg <= 0) return hipErrorInvalidValue;
+    const bool law = pl != PL_NEWTON;
     switch (tile_w) {
     case 64:
-        return powerlaw ? launch_batch_family<64, true>(insts, table, nwg, prefetch, fin, fout, s)
-                        : launch_batch_family<64, false>(insts, table, nwg, prefetch, fin, fout, s);
+        return law ? launch_batch_family<64, true>(insts, table, nwg, pl, prefetch, fin, fout, s)
+                   : launch_batch_family<64, false>(insts, table, nwg, pl, prefetch, fin, fout, s);
     case 128:
-        return powerlaw ? launch_batch_family<128, true>(insts, table, nwg, prefetch, fin, fout, s)
-                        : launch_batch_family<128, false>(insts, table, nwg, prefetch, fin, fout, s);
+        return law ? launch_batch_family<128, true>(insts, table, nwg, pl, prefetch, fin, fout, s)
+                   : launch_batch_family<128, false>(insts, table, nwg, pl, prefetch, fin, fout, s);
     case 256:
-        return powerlaw ? launch_batch_family<256, true>(insts, table, nwg, 2, fin, fout, s)
-                        : launch_batch_family<256, false>(insts, table, nwg, 2, fin, fout, s);
+        return law ? launch_batch_family<256, true>(insts, table, nwg, pl, prefetch, fin, fout, s)
+                   : launch_batch_family<256, false>(insts, table, nwg, pl, prefetch, fin, fout, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -67,8 +68,8 @@ hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, d
         return pl ? launch_fused_family<128, true>(K, G, sh.prefetch, fin, fout, s)
                   : launch_fused_family<128, false>(K, G, sh.prefetch, fin, fout, s);
     case 256:
-        return pl ? launch_fused_family<256, true>(K, G, 2, fin, fout, s)
-                  : launch_fused_family<256, false>(K, G, 2, fin, fout, s);
+        return pl ? launch_fused_family<256, true>(K, G, sh.prefetch, fin, fout, s)
+                  : launch_fused_family<256, false>(K, G, sh.prefetch, fin, fout, s);
     default: return hipErrorInvalidValue;
     }
 }

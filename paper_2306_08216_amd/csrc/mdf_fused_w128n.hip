@@ -5,7 +5,7 @@ namespace mdf {
 
 template hipError_t launch_fused_family<128, false>(const StepConsts&, const fusedk::FusedGrid&, int, const double*,
                                                   double*, hipStream_t);
-template hipError_t launch_batch_family<128, false>(const BatchInst*, const int4*, int, int, const double*, double*,
+template hipError_t launch_batch_family<128, false>(const BatchInst*, const int4*, int, int, int, const double*, double*,
                                                   hipStream_t);
 
 }  // namespace mdf

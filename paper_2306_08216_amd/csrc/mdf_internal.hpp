@@ -64,8 +64,8 @@ struct BatchInst {
 // table entries are (strip, ys0, ys1, instance).
 hipError_t launch_fused2_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int prefetch,
                                const double* fin, double* fout, hipStream_t s);
-hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, bool powerlaw, int tile_w,
-                              int prefetch, const double* fin, double* fout, hipStream_t s);
+hipError_t launch_fused_batch(const BatchInst* insts, const int4* table, int nwg, int pl, int tile_w, int prefetch,
+                              const double* fin, double* fout, hipStream_t s);
 bool fused_shape_ok(const StepConsts& K, FusedShape sh);
 hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, double* fout, hipStream_t s);
 // Same step with one wave per velocity component (64-column strips; tile_w unused).
