@@ -263,11 +263,11 @@ __device__ __forceinline__ double sqrt_refined(double x)
 //           The start is then within 34 % of the root for every g and theta,
 //           and Halley's cubic convergence takes that to a 1-ulp root in three
 //           steps; a fixed count keeps every lane of a wave on the same
-//           instructions.  Each step divides by the hardware reciprocal after
-//           one Newton refinement (relative error ~1e-14 at worst), which only
-//           perturbs the correction itself; the last correction is below 1e-6
-//           of the root.  A root beyond the clamp range is clamped like the
-//           n = 1/2 one.
+//           instructions.  The first two steps divide by the raw hardware
+//           reciprocal: its error perturbs only their corrections, which the
+//           next step's cubic convergence removes.  The last step, whose
+//           correction is below 1e-6 of the root, refines the reciprocal once.
+//           A root beyond the clamp range is clamped like the n = 1/2 one.
 template <int PL>
 __device__ __forceinline__ double powerlaw_nu_sq_t(const StepConsts& K, double q, double theta)
 {
@@ -286,7 +286,10 @@ __device__ __forceinline__ double powerlaw_nu_sq_t(const StepConsts& K, double q
         const double r = Kc * Kc * sqrt_refined(q);
         const unsigned long long rb = static_cast<unsigned long long>(__double_as_longlong(r));
         const double cb = __longlong_as_double(static_cast<long long>(rb / 3ull + (682ull << 52)));
-        double x = fmin(cb, sqrt_refined(r * (1.0 / theta)));
+        // the start needs no accuracy (the steps absorb a relative error of
+        // 2^-8 in it), so sqrt(r/theta) is the raw estimate
+        const double rt = r * (1.0 / theta);
+        double x = fmin(cb, rt * __builtin_amdgcn_rsq(rt));
 #pragma unroll
         for (int it = 0; it < 3; ++it) {
             const double f = x * x * (x + theta) - r;
@@ -294,7 +297,9 @@ __device__ __forceinline__ double powerlaw_nu_sq_t(const StepConsts& K, double q
             const double d2 = 6.0 * x + 2.0 * theta;
             const double den = 2.0 * d1 * d1 - f * d2;
             double y = __builtin_amdgcn_rcp(den);
-            y = fma(y, fma(-den, y, 1.0), y);
+            // an error in the first two corrections is absorbed by the next
+            // step; only the last one needs the refined reciprocal
+            if (it == 2) y = fma(y, fma(-den, y, 1.0), y);
             x -= 2.0 * f * d1 * y;
         }
         nu = rest ? K.nu_min : x;
