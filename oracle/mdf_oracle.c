@@ -47,6 +47,7 @@ struct orc_state {
     size_t n;
     double c, cs2, dt, h;
     double *gx, *gy;          /* derivative scale 1/(X' dxi) at each node */
+    double *met;              /* general mapping: d i/dx, d i/dy, d j/dx, d j/dy planes, or NULL */
     double *Fx, *Fy;          /* body force F_alpha at each node (eq. 2.2.6) */
     double *fhat;             /* state f_hat(t)            */
     double *fhat_plus;        /* f_hat^+(t)   (eq. 2.2.14) */
@@ -332,10 +333,44 @@ static double mixed_d(const orc_state* st, const double* pl, int x, int y, int a
     return eta * central + (1.0 - eta) * upwind;
 }
 
-/* c_j . grad Pi_j with the mixed scheme: only the axis of c_j contributes. */
+/* Mixed difference along an index axis with unit spacing (the general
+ * mapping carries the node spacing in its metric). */
+static double mixed_unit(const orc_state* st, const double* pl, int x, int y, int axis, int sg)
+{
+    int dx = axis == 0 ? 1 : 0, dy = axis == 0 ? 0 : 1;
+    double eta = st->p.eta;
+    double pm1 = at(st, pl, x - dx, y - dy);
+    double p0 = at(st, pl, x, y);
+    double pp1 = at(st, pl, x + dx, y + dy);
+    double central = (pp1 - pm1) / 2.0;
+    double upwind;
+    if (sg >= 0) {
+        double pm2 = at(st, pl, x - 2 * dx, y - 2 * dy);
+        upwind = (3.0 * p0 - 4.0 * pm1 + pm2) / 2.0;
+    } else {
+        double pp2 = at(st, pl, x + 2 * dx, y + 2 * dy);
+        upwind = -(3.0 * p0 - 4.0 * pp1 + pp2) / 2.0;
+    }
+    return eta * central + (1.0 - eta) * upwind;
+}
+
+/* c_j . grad Pi_j with the mixed scheme.  Separable grids: only the axis of
+ * c_j contributes.  General mapping: by the chain rule c_j . grad =
+ * U d/di + V d/dj with the contravariant components U = c_j . grad i and
+ * V = c_j . grad j of the node, each index derivative upwinded by the sign of
+ * its own component (eqs. 2.2.12-2.2.13 along each index line). */
 static double cdotgrad(const orc_state* st, const double* pl, int x, int y, int j)
 {
     double c = st->c;
+    if (st->met) {
+        size_t n = st->n, i = (size_t)y * st->nx + x;
+        double U = c * (CX[j] * st->met[i] + CY[j] * st->met[n + i]);
+        double V = c * (CX[j] * st->met[2 * n + i] + CY[j] * st->met[3 * n + i]);
+        double r = 0.0;
+        if (U != 0.0) r += U * mixed_unit(st, pl, x, y, 0, U > 0.0 ? 1 : -1);
+        if (V != 0.0) r += V * mixed_unit(st, pl, x, y, 1, V > 0.0 ? 1 : -1);
+        return r;
+    }
     if (CX[j] != 0.0) return c * CX[j] * mixed_d(st, pl, x, y, 0, CX[j] > 0 ? 1 : -1);
     if (CY[j] != 0.0) return c * CY[j] * mixed_d(st, pl, x, y, 1, CY[j] > 0 ? 1 : -1);
     return 0.0;
@@ -561,6 +596,7 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     if (!(p->nu > 0.0)) return NULL;
     if (p->pl_n != 1.0 && !(p->nu_min > 0.0 && p->nu_max >= p->nu_min)) return NULL;
     if ((p->inv_dx_x || p->inv_dx_y) && !(p->dx_min > 0.0)) return NULL;
+    if (p->metric && (p->inv_dx_x || p->inv_dx_y || !(p->dx_min > 0.0))) return NULL;
     if (p->force_harmonic != 0 &&
         (p->force_harmonic != 1 || !isfinite(p->force_omega) || !isfinite(p->force_phase)))
         return NULL;
@@ -589,7 +625,13 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     st->p.force_y = NULL;
     for (int i = 0; i < p->nx; ++i) st->gx[i] = p->inv_dx_x ? p->inv_dx_x[i] : 1.0 / hx;
     for (int i = 0; i < p->ny; ++i) st->gy[i] = p->inv_dx_y ? p->inv_dx_y[i] : 1.0 / hy;
-    double dxmin = (p->inv_dx_x || p->inv_dx_y) ? p->dx_min : (hx < hy ? hx : hy);
+    st->met = NULL;
+    if (p->metric) {
+        st->met = (double*)malloc(sizeof(double) * 4 * st->n);
+        for (size_t k = 0; k < 4 * st->n; ++k) st->met[k] = p->metric[k];
+    }
+    st->p.metric = NULL;
+    double dxmin = (p->inv_dx_x || p->inv_dx_y || p->metric) ? p->dx_min : (hx < hy ? hx : hy);
     /* eq. 3.1: dt = CFL dx_min / c; the half step is h = dt/2 (below eq. 2.2.8) */
     st->dt = p->cfl * dxmin / p->c;
     st->h = 0.5 * st->dt;
@@ -624,6 +666,7 @@ void orc_destroy(orc_state* st)
     if (!st) return;
     free(st->gx);
     free(st->gy);
+    free(st->met);
     free(st->Fx);
     free(st->Fy);
     free(st->fhat);
@@ -706,7 +749,9 @@ void orc_derived(const orc_state* st, double* out)
 /* Diagnostics: sum u, sum v, KE = 1/2 sum |u|^2 dA, enstrophy = 1/2 sum omega^2 dA
  * (omega from the local scheme of Sec. 2.4), max |u|, max |div u| by central
  * differences over non-wall nodes, number of non-finite state entries, and
- * sum dA, with dA = 1/(g_x g_y) the area of a node. */
+ * sum dA, with dA = 1/(g_x g_y) the area of a node (under a general mapping
+ * dA = 1/|det| of the node's inverse Jacobian, and the divergence takes both
+ * index differences of each velocity component by the chain rule). */
 void orc_diagnostics(const orc_state* st, double* out)
 {
     int nx = st->nx, ny = st->ny;
@@ -722,6 +767,10 @@ void orc_diagnostics(const orc_state* st, double* out)
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
             double dA = 1.0 / (st->gx[x] * st->gy[y]);
+            if (st->met) {
+                double det = st->met[i] * st->met[3 * n + i] - st->met[n + i] * st->met[2 * n + i];
+                dA = 1.0 / fabs(det);
+            }
             double om = d[12 * n + i];
             su += u[i];
             sv += v[i];
@@ -735,6 +784,14 @@ void orc_diagnostics(const orc_state* st, double* out)
                 int yp = (y + 1) % ny, ym = (y - 1 + ny) % ny;
                 double div = (u[(size_t)y * nx + xp] - u[(size_t)y * nx + xm]) * st->gx[x] / 2.0
                            + (v[(size_t)yp * nx + x] - v[(size_t)ym * nx + x]) * st->gy[y] / 2.0;
+                if (st->met) {
+                    /* du/dx + dv/dy = (di/dx) u_i + (dj/dx) u_j + (di/dy) v_i + (dj/dy) v_j */
+                    double ui = (u[(size_t)y * nx + xp] - u[(size_t)y * nx + xm]) / 2.0;
+                    double uj = (u[(size_t)yp * nx + x] - u[(size_t)ym * nx + x]) / 2.0;
+                    double vi = (v[(size_t)y * nx + xp] - v[(size_t)y * nx + xm]) / 2.0;
+                    double vj = (v[(size_t)yp * nx + x] - v[(size_t)ym * nx + x]) / 2.0;
+                    div = st->met[i] * ui + st->met[2 * n + i] * uj + st->met[n + i] * vi + st->met[3 * n + i] * vj;
+                }
                 if (fabs(div) > dmax) dmax = fabs(div);
             }
         }

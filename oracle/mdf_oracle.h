@@ -45,6 +45,11 @@ typedef struct {
      * with F(x) the uniform part plus the field above, t = steps * dt */
     double  force_omega, force_phase;
     int32_t force_harmonic;
+    /* general (non-separable) coordinate transformation x = X(i, j), y = Y(i, j) of the
+     * node indices: 4 planes of ny*nx entries, d i/dx, d i/dy, d j/dx, d j/dy at each node
+     * (the inverse Jacobian in node units), or NULL.  Excludes inv_dx_x / inv_dx_y; needs
+     * dx_min.  Walls, when given, lie on the index lines i = 0, nx-1 / j = 0, ny-1. */
+    const double* metric;
 } orc_params;
 
 typedef struct orc_state orc_state;

@@ -33,6 +33,7 @@ class OrcParams(C.Structure):
         ("dx_min", C.c_double),
         ("force_x", _dp), ("force_y", _dp),
         ("force_omega", C.c_double), ("force_phase", C.c_double), ("force_harmonic", C.c_int32),
+        ("metric", _dp),
     ]
 
 
@@ -119,11 +120,14 @@ def _params(prob):
     ffy = None if ffy is None else np.ascontiguousarray(ffy, dtype=np.float64)
     for a in (ffx, ffy):
         assert a is None or a.shape == (prob.ny, prob.nx)
-    keep += [gx, gy, ffx, ffy]
+    met = getattr(prob, "metric", None)
+    met = None if met is None else np.ascontiguousarray(met, dtype=np.float64)
+    assert met is None or met.shape == (4, prob.ny, prob.nx)
+    keep += [gx, gy, ffx, ffy, met]
     p = OrcParams(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                   prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
                   prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min, _ptr(ffx), _ptr(ffy),
-                  prob.force_omega, prob.force_phase, int(prob.force_harmonic))
+                  prob.force_omega, prob.force_phase, int(prob.force_harmonic), _ptr(met))
     return p, keep
 
 

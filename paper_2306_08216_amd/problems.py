@@ -58,6 +58,8 @@ class Problem:
     force_harmonic: bool = False           # F(x, t) = F(x) cos(force_omega t + force_phase) (else steady)
     force_omega: float = 0.0
     force_phase: float = 0.0
+    metric: Optional[np.ndarray] = None    # (4, ny, nx): d i/dx, d i/dy, d j/dx, d j/dy (general mapping)
+    node_xy: Optional[tuple] = None        # physical node positions (X, Y) of a general mapping
     name: str = ""
 
     @property
@@ -189,6 +191,76 @@ def pulsed_vortex_amplitude(prob: Problem, t: float, a0: float = 0.0, f0: float 
     k, w = 2.0 * prob.nu, prob.force_omega
     den = k * k + w * w
     return f0 * (k * math.cos(w * t) + w * math.sin(w * t)) / den + (a0 - f0 * k / den) * math.exp(-k * t)
+
+
+def mapping_metric(x_i, x_j, y_i, y_j):
+    """Inverse Jacobian of a mapping of the node indices, (X, Y)(i, j), from its
+    derivatives with respect to the indices: returns the planes d i/dx, d i/dy,
+    d j/dx, d j/dy and the smallest spacing between neighbouring index lines,
+    min(1/|grad i|, 1/|grad j|), the dx_min of the time step."""
+    det = x_i * y_j - x_j * y_i
+    ix, iy, jx, jy = y_j / det, -x_j / det, -y_i / det, x_i / det
+    met = np.stack([ix, iy, jx, jy])
+    dxm = float(min((1.0 / np.hypot(ix, iy)).min(), (1.0 / np.hypot(jx, jy)).min()))
+    return met, dxm
+
+
+def warped_taylor_green(n: int = 32, u0: float = 0.01, nu: float = 0.01, shear: int = 1, eps: float = 0.2,
+                        cfl: float = 0.5, eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+    """Decaying Taylor-Green vortex on a non-orthogonal, non-separable periodic
+    grid: node (i, j) sits at x = xi + shear eta + eps sin(eta), y = eta + eps sin(xi)
+    with xi = 2 pi i/n, eta = 2 pi j/n.  With an integer shear the map carries the
+    index torus onto the [0, 2 pi]^2 torus, so the physical Taylor-Green vortex
+    (taylor_green_exact at the node positions) stays the exact solution."""
+    L = 2.0 * math.pi
+    d = L / n
+    xi, et = np.meshgrid(np.arange(n) * d, np.arange(n) * d, indexing="xy")
+    X = xi + shear * et + eps * np.sin(et)
+    Y = et + eps * np.sin(xi)
+    met, dxm = mapping_metric(np.ones_like(xi) * d, (shear + eps * np.cos(et)) * d, eps * np.cos(xi) * d,
+                              np.ones_like(xi) * d)
+    u = u0 * np.sin(X) * np.cos(Y)
+    v = -u0 * np.cos(X) * np.sin(Y)
+    p = 0.25 * u0 * u0 * (np.cos(2 * X) + np.cos(2 * Y))
+    return Problem(nx=n, ny=n, lx=L, ly=L, nu=nu, u0=u, v0=v, p0=p, cfl=cfl, eta=eta, s_ratio=s_ratio,
+                   metric=met, dx_min=dxm, node_xy=(X, Y), name=f"warped_taylor_green_{n}")
+
+
+def sheared_channel(n: int = 32, nu: float = 0.01, force: float = 1e-4, shear: float = 0.5, cfl: float = 0.5,
+                    eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+    """Force-driven channel (Sec. 4.3) between walls at y = 0 and y = 1, periodic
+    in x with period 1, on a grid whose index lines j = const are the horizontal
+    lines y = j/(n-1) and whose lines i = const are slanted: x = i/n + shear y.
+    The walls are index lines; the steady solution is the Poiseuille profile."""
+    ii, jj = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64), indexing="xy")
+    dx, dy = 1.0 / n, 1.0 / (n - 1)
+    Y = jj * dy
+    X = ii * dx + shear * Y
+    one = np.ones((n, n))
+    met, dxm = mapping_metric(one * dx, one * shear * dy, 0.0 * one, one * dy)
+    z = np.zeros((n, n))
+    return Problem(nx=n, ny=n, lx=1.0, ly=1.0, nu=nu, u0=z, v0=z.copy(), p0=z.copy(), cfl=cfl, eta=eta,
+                   s_ratio=s_ratio, bc_x=PERIODIC, bc_y=WALL, fx=force, metric=met, dx_min=dxm, node_xy=(X, Y),
+                   name=f"sheared_channel_{n}")
+
+
+def trapezoidal_cavity(n: int = 64, re: float = 100.0, lid: float = 0.1, taper: float = 0.4, cfl: float = 0.5,
+                       eta: float = 0.8, s_ratio: float = 1.5) -> Problem:
+    """Lid-driven cavity on a trapezoid (the keyword geometry of the paper): the
+    bottom wall spans x in [0, 1] at y = 0, the lid spans [taper/2, 1 - taper/2]
+    at y = 1, and the side walls are straight; node (i, j) sits at
+    y = j/(n-1), x = 1/2 + (i/(n-1) - 1/2)(1 - taper y).  nu = lid/Re (unit
+    height)."""
+    s = np.arange(n, dtype=np.float64) / (n - 1)
+    S, T = np.meshgrid(s, s, indexing="xy")
+    h = 1.0 / (n - 1)
+    Y = T
+    X = 0.5 + (S - 0.5) * (1.0 - taper * T)
+    met, dxm = mapping_metric((1.0 - taper * T) * h, -taper * (S - 0.5) * h, 0.0 * S, np.ones_like(S) * h)
+    z = np.zeros((n, n))
+    return Problem(nx=n, ny=n, lx=1.0, ly=1.0, nu=lid / re, u0=z, v0=z.copy(), p0=z.copy(), cfl=cfl, eta=eta,
+                   s_ratio=s_ratio, bc_x=WALL, bc_y=WALL, lid_u=lid, metric=met, dx_min=dxm, node_xy=(X, Y),
+                   name=f"trapezoidal_cavity_{n}")
 
 
 def periodic_flow(nx: int = 32, ny: Optional[int] = None, u0: float = 0.1, nu: float = 0.01, cfl: float = 0.5,

@@ -81,6 +81,21 @@ CASES = [
     ("force taken one step late",
      "const double tn = (double)st->steps * st->dt;", "const double tn = (double)(st->steps + 1) * st->dt;",
      "test_oracle_forced", "test_harmonic_force_mean_momentum"),
+    ("mapped transport upwinded by the sign of c_j instead of its contravariant component",
+     "r += U * mixed_unit(st, pl, x, y, 0, U > 0.0 ? 1 : -1);",
+     "r += U * mixed_unit(st, pl, x, y, 0, (CX[j] + CY[j]) > 0.0 ? 1 : -1);",
+     "test_oracle_mapping", "test_warped_taylor_green_decay"),
+    ("contravariant component U built from d j/dx instead of d i/dy",
+     "double U = c * (CX[j] * st->met[i] + CY[j] * st->met[n + i]);",
+     "double U = c * (CX[j] * st->met[i] + CY[j] * st->met[2 * n + i]);",
+     "test_oracle_mapping", "test_warped_taylor_green_decay"),
+    ("mapped node area without the cross terms of the Jacobian",
+     "dA = 1.0 / fabs(det);", "dA = 1.0 / fabs(st->met[i] * st->met[3 * n + i]);",
+     "test_oracle_mapping", "test_warped_taylor_green_decay"),
+    ("mapped divergence without the cross derivatives",
+     "div = st->met[i] * ui + st->met[2 * n + i] * uj + st->met[n + i] * vi + st->met[3 * n + i] * vj;",
+     "div = st->met[i] * ui + st->met[3 * n + i] * vj;",
+     "test_oracle_mapping", "test_divergence_of_a_mapped_field"),
     ("half step with the force not modulated in time",
      "+ st->h * WJ[j] * Fa[a][i] * m;", "+ st->h * WJ[j] * Fa[a][i];",
      "test_oracle_forced", "test_pulsed_vortex_amplitude"),
