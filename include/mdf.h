@@ -76,6 +76,17 @@ typedef struct {
     double  force_omega;     /* angular frequency of the force (time units of nu and dt)          */
     double  force_phase;     /* phase at t = 0                                                      */
     int32_t force_harmonic;  /* 0 or 1                                                              */
+    /* HOST, 4 planes of ny*nx values (x fastest), or NULL: a general (non-separable) coordinate
+     * transformation x = X(i, j), y = Y(i, j) of the node indices, given by its inverse Jacobian
+     * in node units at every node: d i/dx, d i/dy, d j/dx, d j/dy.  Transport then follows the
+     * chain rule, c_j . grad = U d/di + V d/dj with the contravariant components U = c_j . grad i
+     * and V = c_j . grad j, each index derivative by the mixed scheme of eqs. 2.2.12-2.2.13
+     * upwinded by its own component's sign (Sec. 1 names the coordinate transformation and the
+     * trapezoidal cavity; the formulas are this library's reading).  Walls lie on the index lines
+     * i = 0, nx-1 and j = 0, ny-1.  Excludes inv_dx_x / inv_dx_y and needs dx_min > 0; the
+     * values must be finite with a non-zero Jacobian.  Runs on the three-pass step (variant 0)
+     * only; batches and the closure take no general mapping. */
+    const double* metric;
 } mdf_params;
 
 /* Bytes of device workspace a context for these parameters needs, or 0 if the
@@ -161,7 +172,8 @@ mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_w
 
 /* Autotuner for this context: times every fused kernel (variant 1 with
  * tile_w 64, 128 and 256, and variant 2 for a Newtonian fluid; only variant 1
- * with tile_w 64 and prefetch 2 under a force field), prefetch
+ * with tile_w 64 and prefetch 2 under a force field; a general mapping has
+ * only variant 0, which it reports without timing), prefetch
  * depth (2, 3) and eight scalings (0.3..3.5) of the
  * wall-row cost factors of the one-round balanced partition over `steps`
  * steps of the run itself, times the three fastest again over 4 x `steps`

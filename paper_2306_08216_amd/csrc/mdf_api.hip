@@ -64,7 +64,7 @@ mdf_status hip_check(mdf_ctx* c, hipError_t e, const char* what)
 
 struct Layout {
     size_t pitch;                 // nodes per row
-    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, off_seg, off_ff, total;  // bytes
+    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, off_seg, off_ff, off_met, total;  // bytes
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -73,7 +73,7 @@ constexpr int kSegCap = 4096;   // entries of the segment table (one per workgro
 
 bool has_force_field(const mdf_params* p) { return p->force_x != nullptr || p->force_y != nullptr; }
 
-Layout layout_for(int nx, int ny, bool force_field)
+Layout layout_for(int nx, int ny, bool force_field, bool metric)
 {
     Layout L;
     // rows of 80 bytes per node (x-part block, then y-part block); 16-node multiples keep
@@ -92,6 +92,8 @@ Layout layout_for(int nx, int ny, bool force_field)
     L.off_seg = o;  o += align256(kSegCap * sizeof(int4));
     // force field: (F_x, F_y) per node in rows of pitch nodes
     L.off_ff = o;   o += force_field ? align256(2 * L.pitch * (size_t)ny * sizeof(double)) : 0;
+    // general mapping: 4 planes of nx*ny metric values
+    L.off_met = o;  o += metric ? align256(4 * (size_t)nx * (size_t)ny * sizeof(double)) : 0;
     L.total = o;
     return L;
 }
@@ -116,6 +118,8 @@ const char* validate(const mdf_params* p)
     if (p->force_harmonic != 0 && p->force_harmonic != 1) return "force_harmonic must be 0 or 1";
     if (p->force_harmonic && !(std::isfinite(p->force_omega) && std::isfinite(p->force_phase)))
         return "non-finite force_omega or force_phase";
+    if (p->metric && (p->inv_dx_x || p->inv_dx_y)) return "a general mapping (metric) excludes inv_dx_x and inv_dx_y";
+    if (p->metric && !(p->dx_min > 0.0)) return "a general mapping needs dx_min > 0";
     return nullptr;
 }
 
@@ -154,7 +158,7 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.kf = K.w * p.c / K.cs2;
     const double hx = p.bc_x == MDF_BC_WALL ? p.lx / (p.nx - 1) : p.lx / p.nx;
     const double hy = p.bc_y == MDF_BC_WALL ? p.ly / (p.ny - 1) : p.ly / p.ny;
-    const double dxmin = (p.inv_dx_x || p.inv_dx_y) ? p.dx_min : (hx < hy ? hx : hy);
+    const double dxmin = (p.inv_dx_x || p.inv_dx_y || p.metric) ? p.dx_min : (hx < hy ? hx : hy);
     K.dt = p.cfl * dxmin / p.c;
     K.h = 0.5 * K.dt;
     K.eta = p.eta;
@@ -180,7 +184,7 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.q_p = 1.0 / (1.0 + 0.25 * sp * K.dt);
     K.lam_h = 0.5 * K.h * p.c;
     K.lam_dt = 0.5 * K.dt * p.c;
-    K.uniform = (p.inv_dx_x == nullptr && p.inv_dx_y == nullptr) ? 1 : 0;
+    K.uniform = (p.inv_dx_x == nullptr && p.inv_dx_y == nullptr && p.metric == nullptr) ? 1 : 0;
     K.ginv[0] = 1.0 / hx;
     K.ginv[1] = 1.0 / hy;
     K.gx = nullptr;
@@ -201,6 +205,7 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.hw = K.h * K.w;
     K.dw = K.dt * K.w;
     K.ff = nullptr;
+    K.met = nullptr;
     return K;
 }
 
@@ -389,6 +394,7 @@ const char* validate_batch(const mdf_params* ps, int count)
         if (ps[i].inv_dx_x || ps[i].inv_dx_y) return "batched instances must use uniform grids";
         if (has_force_field(&ps[i])) return "batched instances take a uniform force only";
         if (ps[i].force_harmonic) return "batched instances take a steady force only";
+        if (ps[i].metric) return "batched instances take no general mapping";
         if (ps[i].pl_n != ps[0].pl_n) return "batched instances must share the fluid model (pl_n)";
     }
     return nullptr;
@@ -480,7 +486,7 @@ extern "C" {
 size_t mdf_workspace_size(const mdf_params* p)
 {
     if (validate(p)) return 0;
-    return layout_for(p->nx, p->ny, has_force_field(p)).total;
+    return layout_for(p->nx, p->ny, has_force_field(p), p->metric != nullptr).total;
 }
 
 mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0, void* workspace,
@@ -490,7 +496,7 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     *out = nullptr;
     if (const char* why = validate(p)) return fail(nullptr, MDF_EINVAL, "%s", why);
     if (!u0 || !v0 || !p0) return fail(nullptr, MDF_EINVAL, "initial fields must be non-NULL device pointers");
-    const Layout L = layout_for(p->nx, p->ny, has_force_field(p));
+    const Layout L = layout_for(p->nx, p->ny, has_force_field(p), p->metric != nullptr);
     if (!workspace || ws_bytes < L.total)
         return fail(nullptr, MDF_EINVAL, "workspace too small: need %zu bytes, got %zu", L.total, ws_bytes);
     if (((uintptr_t)workspace & 255u) != 0) return fail(nullptr, MDF_EINVAL, "workspace must be 256-byte aligned");
@@ -502,6 +508,7 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     c->p.inv_dx_y = nullptr;
     c->p.force_x = nullptr;
     c->p.force_y = nullptr;
+    c->p.metric = nullptr;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char*)workspace;
     c->ws_bytes = ws_bytes;
@@ -528,6 +535,7 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     // allows, and there one wave per strip is faster.  A force field has
     // kernels of the second kind only.
     c->variant = (p->pl_n == 1.0 && !has_force_field(p)) ? 2 : 1;
+    if (p->metric) c->variant = 0;   // a general mapping runs on the three-pass step
 
     // derivative scales 1/(X' dxi) per node (uniform: 1/dx)
     std::string hbuf;
@@ -587,6 +595,28 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
             return s;
         }
         c->K.ff = dff;
+    }
+    // general mapping: the inverse Jacobian's four planes, finite and invertible at every node
+    if (p->metric) {
+        const size_t n = (size_t)p->nx * p->ny;
+        for (size_t i = 0; i < n; ++i) {
+            const double a = p->metric[i], b = p->metric[n + i], cc = p->metric[2 * n + i], d = p->metric[3 * n + i];
+            const double det = a * d - b * cc;
+            if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(cc) || !std::isfinite(d) || !(det != 0.0) ||
+                !std::isfinite(det)) {
+                delete c;
+                return fail(nullptr, MDF_EINVAL, "metric values must be finite with a non-zero Jacobian");
+            }
+        }
+        double* dmet = (double*)(c->ws + L.off_met);
+        hipError_t e = hipMemcpyAsync(dmet, p->metric, sizeof(double) * 4 * n, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            mdf_status s = hip_check(nullptr, e, "metric upload");
+            delete c;
+            return s;
+        }
+        c->K.met = dmet;
     }
     {
         const mdf_status s = prepare_shape(c);
@@ -689,6 +719,7 @@ mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t s
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
     if (variant < 0 || variant > 2) return fail(c, MDF_EINVAL, "variant must be 0, 1 or 2");
     if (variant == 2 && c->K.ff) return fail(c, MDF_EINVAL, "a force field runs on variant 0 or 1 only");
+    if (variant != 0 && c->K.met) return fail(c, MDF_EINVAL, "a general mapping runs on variant 0 only");
     if (seg_h < -4) return fail(c, MDF_EINVAL, "seg_h below 0 selects 1 to 4 rounds of the balanced table");
     mdf::FusedShape sh = c->shape;
     int rounds = c->rounds;
@@ -761,6 +792,13 @@ mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
     if (steps < 1) return fail(c, MDF_EINVAL, "steps must be >= 1");
+    if (c->K.met) {   // a general mapping has one step kernel: nothing to choose
+        if (choice) {
+            const double ch[6] = {0.0, (double)c->shape.prefetch, c->cx_scale, c->cy_scale, 0.0, (double)c->shape.tile_w};
+            for (int k = 0; k < 6; ++k) choice[k] = ch[k];
+        }
+        return MDF_OK;
+    }
     // state backup in the three-pass scratch buffer (same size as a state buffer)
     const size_t bytes = 10 * (size_t)c->K.pitch * (size_t)c->K.ny * sizeof(double);
     const int cur0 = c->cur;
@@ -941,7 +979,7 @@ mdf_status mdf_closure_apply(mdf_ctx* c, const double* du, const double* dv, dou
                              double* ke_out, double* div_out, int32_t* fell_back)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
-    if (c->p.bc_x != MDF_BC_PERIODIC || c->p.bc_y != MDF_BC_PERIODIC || c->p.inv_dx_x || c->p.inv_dx_y)
+    if (c->p.bc_x != MDF_BC_PERIODIC || c->p.bc_y != MDF_BC_PERIODIC || !c->K.uniform)
         return fail(c, MDF_EINVAL, "the closure applies to periodic uniform grids");
     if ((du == nullptr) != (dv == nullptr)) return fail(c, MDF_EINVAL, "du and dv must both be given or both NULL");
     const double hx = c->p.lx / c->p.nx, hy = c->p.ly / c->p.ny;
@@ -963,7 +1001,7 @@ mdf_status mdf_closure_apply(mdf_ctx* c, const double* du, const double* dv, dou
 static mdf_status closure_async_check(mdf_ctx* c)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
-    if (c->p.bc_x != MDF_BC_PERIODIC || c->p.bc_y != MDF_BC_PERIODIC || c->p.inv_dx_x || c->p.inv_dx_y)
+    if (c->p.bc_x != MDF_BC_PERIODIC || c->p.bc_y != MDF_BC_PERIODIC || !c->K.uniform)
         return fail(c, MDF_EINVAL, "the closure applies to periodic uniform grids");
     return MDF_OK;
 }

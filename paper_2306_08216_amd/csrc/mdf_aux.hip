@@ -63,6 +63,29 @@ __device__ __forceinline__ double transport_at(const StepConsts& K, const double
 {
     const int j = q % 5;
     if (j == 0) return 0.0;
+    if (K.met) {
+        // general mapping: c_j . grad = U d/di + V d/dj with U = c_j . grad i and
+        // V = c_j . grad j at the node, each index difference upwinded by the
+        // sign of its own component
+        const size_t n = (size_t)K.nx * K.ny, i = (size_t)y * K.nx + x;
+        const double cx = j == 1 ? 1.0 : (j == 3 ? -1.0 : 0.0), cy = j == 2 ? 1.0 : (j == 4 ? -1.0 : 0.0);
+        const double U = cx * K.met[i] + cy * K.met[n + i], V = cx * K.met[2 * n + i] + cy * K.met[3 * n + i];
+        const double p0 = fetch(K, f, q, x, y);
+        double r = 0.0;
+        if (U > 0.0)
+            r += transport_pos(K, lam * U, fetch(K, f, q, x - 2, y), fetch(K, f, q, x - 1, y), p0,
+                               fetch(K, f, q, x + 1, y));
+        else if (U < 0.0)
+            r += transport_neg(K, -lam * U, fetch(K, f, q, x - 1, y), p0, fetch(K, f, q, x + 1, y),
+                               fetch(K, f, q, x + 2, y));
+        if (V > 0.0)
+            r += transport_pos(K, lam * V, fetch(K, f, q, x, y - 2), fetch(K, f, q, x, y - 1), p0,
+                               fetch(K, f, q, x, y + 1));
+        else if (V < 0.0)
+            r += transport_neg(K, -lam * V, fetch(K, f, q, x, y - 1), p0, fetch(K, f, q, x, y + 1),
+                               fetch(K, f, q, x, y + 2));
+        return r;
+    }
     if (j == 1 || j == 3) {
         const double lg = lam * gx_at(K, x);
         const double pm1 = fetch(K, f, q, x - 1, y), p0 = fetch(K, f, q, x, y), p1 = fetch(K, f, q, x + 1, y);
@@ -207,7 +230,9 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
         load10(K, f, x, y, fh);
         node_moments(fh, K.c, u, v, P);
         derived_node(K, fh, d);
-        const double dA = 1.0 / (gx_at(K, x) * gy_at(K, y));
+        double dA = 1.0 / (gx_at(K, x) * gy_at(K, y));
+        const size_t nn = (size_t)K.nx * K.ny, ii = (size_t)y * K.nx + x;
+        if (K.met) dA = 1.0 / fabs(K.met[ii] * K.met[3 * nn + ii] - K.met[nn + ii] * K.met[2 * nn + ii]);
         acc[0] += u;
         acc[1] += v;
         acc[2] += 0.5 * (u * u + v * v) * dA;
@@ -225,7 +250,21 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
             node_moments(a, K.c, t0, vn, t2);
             load10(K, f, x, ym, b);
             node_moments(b, K.c, t0, vs, t2);
-            const double div = (ue - uw) * gx_at(K, x) * 0.5 + (vn - vs) * gy_at(K, y) * 0.5;
+            double div = (ue - uw) * gx_at(K, x) * 0.5 + (vn - vs) * gy_at(K, y) * 0.5;
+            if (K.met) {
+                // chain rule: du/dx + dv/dy from both index differences of u and v
+                double un, us, ve, vw;
+                load10(K, f, x, yp, a);
+                node_moments(a, K.c, un, t1, t2);
+                load10(K, f, x, ym, b);
+                node_moments(b, K.c, us, t1, t2);
+                load10(K, f, xp, y, a);
+                node_moments(a, K.c, t0, ve, t2);
+                load10(K, f, xm, y, b);
+                node_moments(b, K.c, t0, vw, t2);
+                div = K.met[ii] * (ue - uw) * 0.5 + K.met[2 * nn + ii] * (un - us) * 0.5 +
+                      K.met[nn + ii] * (ve - vw) * 0.5 + K.met[3 * nn + ii] * (vn - vs) * 0.5;
+            }
             acc[5] = fmax(acc[5], fabs(div));
         }
         int bad = 0;

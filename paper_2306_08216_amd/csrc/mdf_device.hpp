@@ -51,6 +51,8 @@ struct StepConsts {
     // rows of pitch nodes, uniform part included; null for a uniform force.
     // Steps (2) and (4) then add hw F and dw F with hw = h w, dw = dt w.
     const double* ff;
+    // general mapping: 4 planes of nx*ny (d i/dx, d i/dy, d j/dx, d j/dy per node), or null
+    const double* met;
     double hw, dw;
 };
 

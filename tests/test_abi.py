@@ -53,7 +53,9 @@ def test_workspace_size_and_validation(L):
     for bad in (dict(nu=0.0), dict(cfl=-1.0), dict(eta=1.5), dict(nx=4), dict(pl_n=2.0),
                 dict(pl_n=0.5, nu_min=0.0, nu_max=1.0), dict(inv_dx_x=np.ones(16), dx_min=0.0),
                 dict(force_harmonic=2), dict(force_harmonic=True, force_omega=float("nan")),
-                dict(force_harmonic=True, force_phase=float("inf"))):
+                dict(force_harmonic=True, force_phase=float("inf")),
+                dict(metric=np.ones((4, 16, 16)), dx_min=0.0),
+                dict(metric=np.ones((4, 16, 16)), dx_min=0.1, inv_dx_x=np.ones(16))):
         p, keep = _params(L, **bad)
         assert L.mdf_workspace_size(p) == 0, bad
 
@@ -147,6 +149,8 @@ def test_batch_validation_without_device_work(L):
     osc = P.taylor_green(32)
     osc.fx, osc.force_harmonic, osc.force_omega = 1e-4, True, 0.3
     assert L.mdf_batch_workspace_size((L.mdf_params * 2)(good[0], params_of(osc, keep)), 2) == 0
+    warped = P.warped_taylor_green(32)
+    assert L.mdf_batch_workspace_size((L.mdf_params * 2)(good[0], params_of(warped, keep)), 2) == 0
     out = C.c_void_p()
     arrp = (C.c_void_p * 3)()
     s = L.lib().mdf_batch_init(arr, 3, arrp, arrp, arrp, None, 0, None, C.byref(out))
