@@ -33,6 +33,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_NODE = 160.0         # 10 FP64 planes read + 10 written per node and step
+# The three-pass step of a general (non-separable) mapping, per node: pass A reads f_hat and
+# writes f_bar^+ (160 B), pass B reads f_bar^+ and the 4 metric values and writes f(t+h)
+# (192 B), pass C reads f_hat, f(t+h) and the metric and writes f_hat(t+dt) (272 B).
+MAPPED_THREE_PASS_BYTES = 624.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2306_08216_amd", "csrc")
 TUNING = os.path.join(ROOT, "paper_2306_08216_amd", "tuning_mi355x.json")
@@ -241,7 +245,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200, help="untimed steps before the timed ones")
     ap.add_argument("--prerun", type=int, default=1000,
                     help="steps from rest that prepare the input state of the power-law and cavity workloads")
-    ap.add_argument("--workload", choices=["powerlaw", "cavity", "taylor-green", "batch"], default="powerlaw",
+    ap.add_argument("--workload", choices=["powerlaw", "cavity", "taylor-green", "batch", "trapezoid"],
+                    default="powerlaw",
                     help="powerlaw: the benchmarked stretched power-law cavity (both indices unless --pl-n); "
                          "cavity: lid-driven cavity Re 1000; taylor-green: periodic decaying vortex; "
                          "batch: 256 periodic decaying-vortex instances of sizes 64..512 advanced together")
@@ -309,6 +314,11 @@ def main():
             prob = P.cavity(n, re=1000.0, lid=0.1)
             wl = f"lid-driven cavity Re 1000, {n}x{n} nodes, lid 0.1, state pre-run {args.prerun} steps from rest, FP64"
             prerun = args.prerun
+        elif args.workload == "trapezoid":
+            prob = P.trapezoidal_cavity(n, re=100.0, lid=0.1)
+            wl = (f"lid-driven trapezoidal cavity Re 100 (general mapping, three-pass step), {n}x{n} nodes, "
+                  f"taper 0.4, lid 0.1, state pre-run {args.prerun} steps from rest, FP64")
+            prerun = args.prerun
         else:
             prob = P.taylor_green(n, u0=0.01, nu=0.01)
             wl = f"periodic Taylor-Green vortex, {n}x{n} nodes, u0 0.01, nu 0.01, FP64"
@@ -320,15 +330,16 @@ def main():
     nodes = sum(r["nodes"] for r in runs)
     ms_per_step = sum(r["ms_per_step"] for r in runs)     # one step of every run
     mlups = nodes / (ms_per_step / 1e3) / 1e6
-    achieved = BYTES_PER_NODE * nodes / (ms_per_step / 1e3) / 1e9
+    bpn = MAPPED_THREE_PASS_BYTES if args.workload == "trapezoid" else BYTES_PER_NODE
+    achieved = bpn * nodes / (ms_per_step / 1e3) / 1e9
     per_run = {}
     for r, prob in zip(runs, probs):
         key = stem.get(prob.pl_n, args.workload)
         traffic = measured_traffic(key, n, r["choice"])
         per_run[r["label"]] = {
             "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "region_ms_per_step": r["region_ms_per_step"],
-            "achieved_GBs": round(BYTES_PER_NODE * r["nodes"] / (r["ms_per_step"] / 1e3) / 1e9, 1),
-            "frac": round(BYTES_PER_NODE * r["nodes"] / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "achieved_GBs": round(bpn * r["nodes"] / (r["ms_per_step"] / 1e3) / 1e9, 1),
+            "frac": round(bpn * r["nodes"] / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": traffic, "kernel_choice": r["tuned"] or r["choice"], "diagnostics": r["diagnostics"],
             "wall_s": round(r["wall_s"], 4)}
 
@@ -374,7 +385,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * runs[0]["nodes"],
+                     "algorithmic_bytes_per_launch": bpn * runs[0]["nodes"],
                      "kernel": kname,
                      "copy_ceiling": copy,
                      "frac_of_copy": round(achieved / copy["GB/s"], 4)},
@@ -386,7 +397,8 @@ def main():
 
 
 def secondary_lines(args):
-    """Context lines: the 1024^2 cavity (cache-resident pair) and the batch."""
+    """Context lines: the 1024^2 cavity (cache-resident pair), the batch, and the
+    trapezoidal cavity on a general mapping (three-pass step)."""
     from paper_2306_08216_amd import problems as P
 
     class A:
@@ -404,7 +416,16 @@ def secondary_lines(args):
            "kernel_choice": r["tuned"], "steps": a.steps}
     a.steps = min(args.steps, 500)
     bat = bench_batch(a)
-    return {"cavity1024": cav, "batch256": bat}
+    a.steps, a.variant = min(args.steps, 500), 0
+    prob = P.trapezoidal_cavity(2048, re=100.0, lid=0.1)
+    r = run_solver(prob, a, "trapezoid2048", 1000)
+    gbs = MAPPED_THREE_PASS_BYTES * prob.nodes / (r["ms_per_step"] / 1e3) / 1e9
+    trap = {"workload": "lid-driven trapezoidal cavity Re 100 on a general (non-separable) mapping, 2048x2048, "
+                        "three-pass step (624 B per node: f_hat read twice, two intermediates written and read, "
+                        "the metric read twice)",
+            "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "achieved_GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "steps": a.steps, "diagnostics": r["diagnostics"]}
+    return {"cavity1024": cav, "batch256": bat, "trapezoid2048": trap}
 
 
 def bench_batch(args):

@@ -311,10 +311,35 @@ __global__ void k_unpack(StepConsts K, const double* __restrict__ dense, double*
     store_node(f, K.pitch, x, y, phi);
 }
 
+// wall nodes of the perimeter: rows y = 0, ny-1 (y walls), then columns
+// x = 0, nx-1 (x walls) without the corners the rows already hold
+__device__ __forceinline__ bool perimeter_node(const StepConsts& K, int i, int& x, int& y)
+{
+    const int nrow = K.bcy ? 2 * K.nx : 0;
+    if (i < nrow) {
+        x = i % K.nx;
+        y = i < K.nx ? 0 : K.ny - 1;
+        return true;
+    }
+    i -= nrow;
+    const int ncol = K.bcy ? K.ny - 2 : K.ny;
+    if (K.bcx && i < 2 * ncol) {
+        y = (K.bcy ? 1 : 0) + i % ncol;
+        x = i < ncol ? 0 : K.nx - 1;
+        return true;
+    }
+    return false;
+}
+
+inline int perimeter_count(const StepConsts& K)
+{
+    return (K.bcy ? 2 * K.nx : 0) + (K.bcx ? 2 * (K.bcy ? K.ny - 2 : K.ny) : 0);
+}
+
 // ---- three-pass reference step ----
 
 // pass A: f_bar^+ at every node (Step (1), eq. 2.2.15); wall nodes by the wall rule
-__global__ void k_pass_a(StepConsts K, const double* __restrict__ fh, double* __restrict__ fbp)
+__global__ __launch_bounds__(256) void k_pass_a(StepConsts K, const double* __restrict__ fh, double* __restrict__ fbp)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= K.nx || y >= K.ny) return;
@@ -344,21 +369,36 @@ __device__ __forceinline__ void mid_at(const StepConsts& K, const double* fbp, i
     collide3(K, fb, f);
 }
 
-__global__ void k_pass_b(StepConsts K, const double* __restrict__ fbp, double* __restrict__ fmid)
+// Wall nodes (one thread per perimeter node; the interior is k_pass_tiled):
+// a wall node extrapolates from its two inward neighbours, and one loop over
+// them keeps a single inlined copy of the node update (three copies spilled
+// to scratch).
+__global__ __launch_bounds__(256) void k_pass_b(StepConsts K, const double* __restrict__ fbp,
+                                                double* __restrict__ fmid)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= K.nx || y >= K.ny) return;
+    int x, y;
+    if (!perimeter_node(K, (int)(blockIdx.x * blockDim.x + threadIdx.x), x, y)) return;
     int x1, y1, x2, y2;
-    double uw, out[10];
-    if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
-        double p1[10], p2[10];
-        mid_at(K, fbp, x1, y1, p1);
-        mid_at(K, fbp, x2, y2, p2);
-        wall_extrapolate(K, p1, p2, uw, out);
-    } else {
-        mid_at(K, fbp, x, y, out);
+    double uw = 0.0, p1[10], p2[10];
+    const bool wall = wall_neighbours(K, x, y, x1, y1, x2, y2, uw);
+    const int cnt = wall ? 2 : 1;
+#pragma nounroll
+    for (int t = 0; t < cnt; ++t) {
+        double v[10];
+        mid_at(K, fbp, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            if (t == 0) p1[k] = v[k];
+            else p2[k] = v[k];
+        }
     }
-    store10(K, fmid, x, y, out);
+    if (wall) {
+        double out[10];
+        wall_extrapolate(K, p1, p2, uw, out);
+        store10(K, fmid, x, y, out);
+    } else {
+        store10(K, fmid, x, y, p1);
+    }
 }
 
 // f_hat(t+dt) at an interior node: Step (4), eq. 2.3.24
@@ -372,22 +412,142 @@ __device__ __forceinline__ void full_at(const StepConsts& K, const double* fh, c
     for (int k = 0; k < 10; ++k) out[k] = fhp[k] - transport_at(K, fmid, k, x, y, K.lam_dt) + dwf_at(K, x, y, k / 5);
 }
 
-__global__ void k_pass_c(StepConsts K, const double* __restrict__ fh, const double* __restrict__ fmid,
-                         double* __restrict__ fnew)
+__global__ __launch_bounds__(256) void k_pass_c(StepConsts K, const double* __restrict__ fh,
+                                                const double* __restrict__ fmid, double* __restrict__ fnew)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= K.nx || y >= K.ny) return;
+    int x, y;
+    if (!perimeter_node(K, (int)(blockIdx.x * blockDim.x + threadIdx.x), x, y)) return;
     int x1, y1, x2, y2;
-    double uw, out[10];
-    if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
-        double p1[10], p2[10];
-        full_at(K, fh, fmid, x1, y1, p1);
-        full_at(K, fh, fmid, x2, y2, p2);
-        wall_extrapolate(K, p1, p2, uw, out);
-    } else {
-        full_at(K, fh, fmid, x, y, out);
+    double uw = 0.0, p1[10], p2[10];
+    const bool wall = wall_neighbours(K, x, y, x1, y1, x2, y2, uw);
+    const int cnt = wall ? 2 : 1;
+#pragma nounroll
+    for (int t = 0; t < cnt; ++t) {
+        double v[10];
+        full_at(K, fh, fmid, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            if (t == 0) p1[k] = v[k];
+            else p2[k] = v[k];
+        }
     }
-    store10(K, fnew, x, y, out);
+    if (wall) {
+        double out[10];
+        wall_extrapolate(K, p1, p2, uw, out);
+        store10(K, fnew, x, y, out);
+    } else {
+        store10(K, fnew, x, y, p1);
+    }
+}
+
+// ---- tiled sub-steps of the three-pass step (interior nodes) ----
+// A 64 x 4 tile of nodes stages its input field with a halo of 2 in LDS, so
+// each stencil value is loaded from memory once per tile instead of once per
+// use; the stencil then reads LDS.  Wall nodes keep the per-node code above
+// (k_pass_b / k_pass_c over the perimeter only).
+constexpr int TB_X = 64, TB_Y = 4, TB_HALO = 2;
+constexpr int TS_X = TB_X + 2 * TB_HALO, TS_Y = TB_Y + 2 * TB_HALO;
+
+// All 10 components of node (x, y) of a stored field for the tile: wrapped on
+// a periodic axis, the quadratic ghost one node beyond a wall; positions a
+// stencil never reads (further beyond a wall, or beyond two walls) get zeros.
+__device__ __forceinline__ void tile_node(const StepConsts& K, const double* f, int x, int y, double* phi)
+{
+    if (!K.bcx) x = ((x % K.nx) + K.nx) % K.nx;
+    if (!K.bcy) y = ((y % K.ny) + K.ny) % K.ny;
+    const bool out_x = x < 0 || x >= K.nx, out_y = y < 0 || y >= K.ny;
+    if (x < -1 || x > K.nx || y < -1 || y > K.ny || (out_x && out_y)) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) phi[q] = 0.0;
+        return;
+    }
+    if (!out_x && !out_y) {
+        load_node(f, K.pitch, x, y, phi);
+        return;
+    }
+    // one node beyond a wall: ghost from the wall node and the next two inward
+    int x0 = x, y0 = y, dx = 0, dy = 0;
+    if (x == -1) x0 = 0, dx = 1;
+    if (x == K.nx) x0 = K.nx - 1, dx = -1;
+    if (y == -1) y0 = 0, dy = 1;
+    if (y == K.ny) y0 = K.ny - 1, dy = -1;
+    double a[10], b[10], c[10];
+    load_node(f, K.pitch, x0, y0, a);
+    load_node(f, K.pitch, x0 + dx, y0 + dy, b);
+    load_node(f, K.pitch, x0 + 2 * dx, y0 + 2 * dy, c);
+#pragma unroll
+    for (int q = 0; q < 10; ++q) phi[q] = ghost(a[q], b[q], c[q]);
+}
+
+// tau c_j . grad Pi_j of component q at tile position (cx, cy), node (x, y)
+__device__ __forceinline__ double transport_tile(const StepConsts& K, const double (*t)[TS_X], int cx, int cy, int q,
+                                                 int x, int y, double lam)
+{
+    const int j = q % 5;
+    if (j == 0) return 0.0;
+    double U, V;
+    if (K.met) {
+        const size_t n = (size_t)K.nx * K.ny, i = (size_t)y * K.nx + x;
+        const double ex = j == 1 ? 1.0 : (j == 3 ? -1.0 : 0.0), ey = j == 2 ? 1.0 : (j == 4 ? -1.0 : 0.0);
+        U = ex * K.met[i] + ey * K.met[n + i];
+        V = ex * K.met[2 * n + i] + ey * K.met[3 * n + i];
+    } else {
+        U = j == 1 ? gx_at(K, x) : (j == 3 ? -gx_at(K, x) : 0.0);
+        V = j == 2 ? gy_at(K, y) : (j == 4 ? -gy_at(K, y) : 0.0);
+    }
+    double r = 0.0;
+    if (U > 0.0)
+        r += transport_pos(K, lam * U, t[cy][cx - 2], t[cy][cx - 1], t[cy][cx], t[cy][cx + 1]);
+    else if (U < 0.0)
+        r += transport_neg(K, -lam * U, t[cy][cx - 1], t[cy][cx], t[cy][cx + 1], t[cy][cx + 2]);
+    if (V > 0.0)
+        r += transport_pos(K, lam * V, t[cy - 2][cx], t[cy - 1][cx], t[cy][cx], t[cy + 1][cx]);
+    else if (V < 0.0)
+        r += transport_neg(K, -lam * V, t[cy - 1][cx], t[cy][cx], t[cy + 1][cx], t[cy + 2][cx]);
+    return r;
+}
+
+// FULL = false: pass B (half step of f_bar^+, then Step (3)) into f(t+h);
+// FULL = true: pass C (Step (4) on f(t+h) with f_hat^+ recomputed from f_hat).
+template <bool FULL>
+__global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const double* __restrict__ src,
+                                                           const double* __restrict__ fh, double* __restrict__ dst)
+{
+    __shared__ double tile[10][TS_Y][TS_X];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int ox = (int)blockIdx.x * TB_X - TB_HALO, oy = (int)blockIdx.y * TB_Y - TB_HALO;
+    for (int idx = ty * TB_X + tx; idx < TS_X * TS_Y; idx += TB_X * TB_Y) {
+        const int ly = idx / TS_X, lx = idx - ly * TS_X;
+        double phi[10];
+        tile_node(K, src, ox + lx, oy + ly, phi);
+#pragma unroll
+        for (int q = 0; q < 10; ++q) tile[q][ly][lx] = phi[q];
+    }
+    __syncthreads();
+    const int x = (int)blockIdx.x * TB_X + tx, y = (int)blockIdx.y * TB_Y + ty;
+    if (x >= K.nx || y >= K.ny || is_wall(K, x, y)) return;
+    const int cx = tx + TB_HALO, cy = ty + TB_HALO;
+    double base[10], out[10];
+    if (FULL) {
+        double a[10];
+        load_node(fh, K.pitch, x, y, a);
+        collide1_hat(K, a, base);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) base[q] = tile[q][cy][cx];
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        const double tr = transport_tile(K, tile[q], cx, cy, q, x, y, FULL ? K.lam_dt : K.lam_h);
+        out[q] = base[q] - tr + (FULL ? dwf_at(K, x, y, q / 5) : hwf_at(K, x, y, q / 5));
+    }
+    if (FULL) {
+        store_node(dst, K.pitch, x, y, out);
+    } else {
+        double fm[10];
+        collide3(K, out, fm);
+        store_node(dst, K.pitch, x, y, fm);
+    }
 }
 
 inline dim3 grid2d(const StepConsts& K, dim3 b) { return dim3((K.nx + b.x - 1) / b.x, (K.ny + b.y - 1) / b.y); }
@@ -485,10 +645,13 @@ hipError_t launch_unpack(const StepConsts& K, const double* dense, double* f, hi
 hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew,
                              hipStream_t s)
 {
-    const dim3 b(64, 4);
+    const dim3 b(64, 4), bt(TB_X, TB_Y);
+    const int nper = perimeter_count(K);
     hipLaunchKernelGGL(k_pass_a, grid2d(K, b), b, 0, s, K, fh, fbp);
-    hipLaunchKernelGGL(k_pass_b, grid2d(K, b), b, 0, s, K, fbp, fmid);
-    hipLaunchKernelGGL(k_pass_c, grid2d(K, b), b, 0, s, K, fh, fmid, fnew);
+    hipLaunchKernelGGL(k_pass_tiled<false>, grid2d(K, bt), bt, 0, s, K, fbp, nullptr, fmid);
+    if (nper > 0) hipLaunchKernelGGL(k_pass_b, dim3((nper + 255) / 256), dim3(256), 0, s, K, fbp, fmid);
+    hipLaunchKernelGGL(k_pass_tiled<true>, grid2d(K, bt), bt, 0, s, K, fmid, fh, fnew);
+    if (nper > 0) hipLaunchKernelGGL(k_pass_c, dim3((nper + 255) / 256), dim3(256), 0, s, K, fh, fmid, fnew);
     return hipGetLastError();
 }
 
