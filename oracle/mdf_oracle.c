@@ -56,8 +56,17 @@ struct orc_state {
     double *fmid;             /* f(t+h)       (eq. 2.2.16) */
     double *fnew;             /* f_hat(t+dt)  (eq. 2.3.24) */
     double mats[125];         /* Newtonian collision matrices */
+    double *R;                /* mass source R at each node (eq. 2.1.1), or NULL */
+    double kinv[4][25];       /* (I + kappa Lambda~)^-1 of the four stored forms (with R) */
+    double kap[4];            /* their kappa: dt/2, h/2, -h/2, 0 */
+    /* alpha = 0 distributions (rho0), when tracked: f_hat, f_hat^+, f_bar^+, f_bar, f, new */
+    double *r0hat, *r0hatp, *r0barp, *r0bar, *r0mid, *r0new;
     int64_t steps;
 };
+
+/* stored forms phi = f + kappa Lambda~ (f - f^eq): f_hat (eq. 2.2.2), f_bar (eq. 2.2.9a),
+ * f_bar^+ (eq. 2.2.9b), f itself */
+enum { FORM_HAT = 0, FORM_BAR = 1, FORM_BARPLUS = 2, FORM_F = 3 };
 
 /* ------------------------------------------------------------------ */
 /* small dense linear algebra                                          */
@@ -167,6 +176,78 @@ void orc_feq(double c, double u, double v, double P, double* out)
             out[a * NQ + j] = WJ[j] * (ua[a] + cdot / cs2);
         }
     }
+}
+
+/* Pressure of eq. 2.3.23 with the mass source R, at a node whose stored
+ * distributions are phi = f + kappa Lambda~ (f - f^eq(u, P)):
+ *   P = (sum_alpha sum_j c_{j,alpha} f_{j,alpha} + (c_s^2/s) R - |u|^2) / d,  d = 2,
+ * where f itself follows from phi and P through
+ *   f = (I + kappa Lambda~)^{-1} (phi + kappa Lambda~ f^eq(u, P))     (Minv below).
+ * The definition is therefore an equation in P.  Its residual
+ *   r(P) = P - (sum c f(P) + (c_s^2/s) R - |u|^2) / 2
+ * is affine in P (f^eq is linear in P), so the root is r(0) / (r(0) - r(1)).
+ * u and v are the zeroth moments of phi (Lambda~ keeps them, eq. 2.2.4), and
+ * c_s^2/s = nu (eq. 2.3.14) for the Newtonian fluid this needs. */
+static double solve_pressure(const orc_state* st, const double* phi, const double* Minv, double kappa, double R,
+                             double u, double v)
+{
+    const double* Lt = st->mats; /* Lambda~ */
+    double r[2];
+    for (int k = 0; k < 2; ++k) {
+        const double Ptry = (double)k;
+        double fe[NPL], T = 0.0;
+        orc_feq(st->c, u, v, Ptry, fe);
+        for (int a = 0; a < 2; ++a) {
+            double lf[NQ], rhs[NQ], f[NQ];
+            mv5(Lt, fe + a * NQ, lf);
+            for (int q = 0; q < NQ; ++q) rhs[q] = phi[a * NQ + q] + kappa * lf[q];
+            mv5(Minv, rhs, f);
+            for (int q = 0; q < NQ; ++q) T += st->c * (a == 0 ? CX[q] : CY[q]) * f[q];
+        }
+        r[k] = Ptry - 0.5 * (T + st->p.nu * R - (u * u + v * v));
+    }
+    return r[0] / (r[0] - r[1]);
+}
+
+static double form_kappa(const orc_state* st, int form)
+{
+    return form == FORM_HAT ? 0.5 * st->dt : form == FORM_BAR ? 0.5 * st->h : form == FORM_BARPLUS ? -0.5 * st->h : 0.0;
+}
+
+static void form_inverse(const orc_state* st, int form, double* Minv)
+{
+    double M[25];
+    const double kappa = form_kappa(st, form);
+    for (int k = 0; k < 25; ++k) M[k] = ((k % 6) == 0 ? 1.0 : 0.0) + kappa * st->mats[k];
+    inv5(M, Minv);
+}
+
+double orc_form_pressure(const orc_state* st, const double* phi, int32_t form, double R)
+{
+    if (form < 0 || form > 3 || st->p.pl_n != 1.0) return NAN;
+    double u, v, Pform, Minv[25];
+    orc_node_moments(st->c, phi, &u, &v, &Pform);
+    form_inverse(st, form, Minv);
+    return solve_pressure(st, phi, Minv, form_kappa(st, form), R, u, v);
+}
+
+/* u, v and P of a stored form at a node with mass source R: for R = 0 the
+ * pressure sum evaluated on the form itself (orc_node_moments); else the
+ * solve above, with the form's inverse taken once at set-up. */
+static void node_state(const orc_state* st, const double* phi, int form, double R, double* u, double* v, double* P)
+{
+    orc_node_moments(st->c, phi, u, v, P);
+    if (R == 0.0) return;
+    *P = solve_pressure(st, phi, st->kinv[form], st->kap[form], R, *u, *v);
+}
+
+static double source_at(const orc_state* st, size_t i) { return st->R ? st->R[i] : 0.0; }
+
+/* Equilibrium of the alpha = 0 equation (eq. 2.2.5 with u_bar_0 = rho0 and
+ * E_0 = 0): f^eq_{j,0} = w_j [rho0 + c_j . (rho0 u) / c_s^2]. */
+static void feq_rho0(double c, double cs2, double rho, double u, double v, double* out)
+{
+    for (int j = 0; j < NQ; ++j) out[j] = WJ[j] * (rho + c * (CX[j] * u + CY[j] * v) * rho / cs2);
 }
 
 /* MRT collision matrix Lambda~ = M^-1 S M (eq. 2.2.4, Sec. 3.1 rates
@@ -405,7 +486,7 @@ static void scatter(const orc_state* st, double* field, size_t i, const double* 
  * extrapolation keeps the scheme second order at walls, as the GREs of the
  * Poiseuille table require (a zeroth-order copy of Pi(n1) - f^eq(n1) gives a
  * first-order wall error about 16 times the tabulated value at 32 x 32). */
-void orc_wall_update(const orc_state* st, double* field)
+static void wall_update(const orc_state* st, double* field, int form)
 {
     const orc_params* p = &st->p;
     int nx = st->nx, ny = st->ny;
@@ -423,8 +504,8 @@ void orc_wall_update(const orc_state* st, double* field)
             double u1, v1, P1, u2, v2, P2;
             gather(st, field, i1, ph1);
             gather(st, field, i2, ph2);
-            orc_node_moments(st->c, ph1, &u1, &v1, &P1);
-            orc_node_moments(st->c, ph2, &u2, &v2, &P2);
+            node_state(st, ph1, form, source_at(st, i1), &u1, &v1, &P1);
+            node_state(st, ph2, form, source_at(st, i2), &u2, &v2, &P2);
             orc_feq(st->c, u1, v1, P1, fe1);
             orc_feq(st->c, u2, v2, P2, fe2);
             orc_feq(st->c, uw, 0.0, P1, few);
@@ -435,14 +516,16 @@ void orc_wall_update(const orc_state* st, double* field)
         }
 }
 
+void orc_wall_update(const orc_state* st, double* field) { wall_update(st, field, FORM_HAT); }
+
 /* ------------------------------------------------------------------ */
 /* Step (1): collision at t (eqs. 2.2.14 and 2.2.15)                    */
 /* ------------------------------------------------------------------ */
 
-void orc_collide_step1(const orc_state* st, const double* fhat, double* fhat_plus, double* fbar_plus)
+static void collide_step1(const orc_state* st, const double* fhat, double R, double* fhat_plus, double* fbar_plus)
 {
     double u, v, P, feq[NPL], scratch[125];
-    orc_node_moments(st->c, fhat, &u, &v, &P);
+    node_state(st, fhat, FORM_HAT, R, &u, &v, &P);
     orc_feq(st->c, u, v, P, feq);
     double nu = node_nu(st, fhat, feq, st->cs2 * st->dt / 2.0);
     const double* mats = node_mats(st, nu, scratch);
@@ -468,11 +551,17 @@ void orc_collide_step1(const orc_state* st, const double* fhat, double* fhat_plu
     }
 }
 
+/* the same at a node without mass source */
+void orc_collide_step1(const orc_state* st, const double* fhat, double* fhat_plus, double* fbar_plus)
+{
+    collide_step1(st, fhat, 0.0, fhat_plus, fbar_plus);
+}
+
 /* Step (3): f = (I + h/2 Lambda~)^-1 (f_bar + h/2 Lambda~ f^eq)   (eq. 2.2.16) */
-static void collide_step3(const orc_state* st, const double* fbar, double* f)
+static void collide_step3(const orc_state* st, const double* fbar, double R, double* f)
 {
     double u, v, P, feq[NPL], scratch[125];
-    orc_node_moments(st->c, fbar, &u, &v, &P);
+    node_state(st, fbar, FORM_BAR, R, &u, &v, &P);
     orc_feq(st->c, u, v, P, feq);
     double nu = node_nu(st, fbar, feq, st->cs2 * st->dt / 4.0);
     const double* mats = node_mats(st, nu, scratch);
@@ -485,6 +574,95 @@ static void collide_step3(const orc_state* st, const double* fbar, double* f)
         mv5(Cinv, rhs, out);
         for (int j = 0; j < NQ; ++j) f[a * NQ + j] = out[j];
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* the alpha = 0 equation (rho0), tracked as a check of Remark 1        */
+/* ------------------------------------------------------------------ */
+
+/* Steps (1)-(4) for the alpha = 0 distributions: the same collision matrices
+ * and stencils as the velocity sets, the equilibrium of feq_rho0 with the
+ * velocity of the velocity sets at t (Step 1) and t + h (Step 3), and the
+ * source F_{j,0} = w_j R (eq. 2.2.6 with F_bar_0 = R, eq. 2.1.2).  No pressure
+ * enters (E_0 = 0).  Runs after the velocity sets' step, whose f_hat(t) and
+ * f(t+h) it reads. */
+static void rho0_step(orc_state* st)
+{
+    int nx = st->nx, ny = st->ny;
+    size_t n = st->n;
+    const double* Lt = st->mats;
+    const double* ImL = st->mats + 25;
+    const double* Ib = st->mats + 50;
+    const double* Cinv = st->mats + 75;
+    double lam[25], lam34[25];
+    for (int k = 0; k < 25; ++k) {
+        double id = (k % 6) == 0 ? 1.0 : 0.0;
+        lam[k] = id - ImL[k];
+        lam34[k] = id - Ib[k];
+    }
+    /* Step (1) */
+    for (size_t i = 0; i < n; ++i) {
+        double g[NQ], fe[NQ], t1[NQ], t2[NQ], rho = 0.0, u = 0.0, v = 0.0;
+        for (int q = 0; q < NQ; ++q) {
+            g[q] = st->r0hat[q * n + i];
+            rho += g[q];
+            u += st->fhat[q * n + i];
+            v += st->fhat[(NQ + q) * n + i];
+        }
+        feq_rho0(st->c, st->cs2, rho, u, v, fe);
+        mv5(ImL, g, t1);
+        mv5(lam, fe, t2);
+        for (int q = 0; q < NQ; ++q) st->r0hatp[q * n + i] = t1[q] + t2[q];
+        mv5(Ib, g, t1);
+        mv5(lam34, fe, t2);
+        for (int q = 0; q < NQ; ++q) st->r0barp[q * n + i] = t1[q] + t2[q];
+    }
+    /* Step (2) */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t i = (size_t)y * nx + x;
+            for (int q = 0; q < NQ; ++q) {
+                const double* pl = st->r0barp + q * n;
+                st->r0bar[q * n + i] = pl[i] - st->h * cdotgrad(st, pl, x, y, q) + st->h * WJ[q] * source_at(st, i);
+            }
+        }
+    /* Step (3) */
+    for (size_t i = 0; i < n; ++i) {
+        double g[NQ], fe[NQ], lf[NQ], rhs[NQ], out[NQ], rho = 0.0, u = 0.0, v = 0.0;
+        for (int q = 0; q < NQ; ++q) {
+            g[q] = st->r0bar[q * n + i];
+            rho += g[q];
+            u += st->fmid[q * n + i];
+            v += st->fmid[(NQ + q) * n + i];
+        }
+        feq_rho0(st->c, st->cs2, rho, u, v, fe);
+        mv5(Lt, fe, lf);
+        for (int q = 0; q < NQ; ++q) rhs[q] = g[q] + 0.5 * st->h * lf[q];
+        mv5(Cinv, rhs, out);
+        for (int q = 0; q < NQ; ++q) st->r0mid[q * n + i] = out[q];
+    }
+    /* Step (4) */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t i = (size_t)y * nx + x;
+            for (int q = 0; q < NQ; ++q)
+                st->r0new[q * n + i] = st->r0hatp[q * n + i] - st->dt * cdotgrad(st, st->r0mid + q * n, x, y, q)
+                                     + st->dt * WJ[q] * source_at(st, i);
+        }
+    double* t = st->r0hat;
+    st->r0hat = st->r0new;
+    st->r0new = t;
+}
+
+int32_t orc_rho0(const orc_state* st, double* out)
+{
+    if (!st->r0hat) return -1;
+    for (size_t i = 0; i < st->n; ++i) {
+        double rho = 0.0;
+        for (int q = 0; q < NQ; ++q) rho += st->r0hat[q * st->n + i];
+        out[i] = rho;
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -508,11 +686,11 @@ static void one_step(orc_state* st)
     for (long i = 0; i < n; ++i) {
         double fh[NPL], fhp[NPL], fbp[NPL];
         gather(st, st->fhat, i, fh);
-        orc_collide_step1(st, fh, fhp, fbp);
+        collide_step1(st, fh, source_at(st, (size_t)i), fhp, fbp);
         scatter(st, st->fhat_plus, i, fhp);
         scatter(st, st->fbar_plus, i, fbp);
     }
-    orc_wall_update(st, st->fbar_plus);
+    wall_update(st, st->fbar_plus, FORM_BARPLUS);
 
     /* Step (2): f_bar(t+h) = f_bar^+ - h c_j . grad f_bar^+ + h w_j F_alpha(t)
      * (eq. 2.3.25: eq. 2.2.11 with the G terms and the h^2/2 d_t F term dropped
@@ -538,10 +716,10 @@ static void one_step(orc_state* st)
             size_t i = (size_t)y * nx + x;
             double fb[NPL], f[NPL];
             gather(st, st->fbar, i, fb);
-            collide_step3(st, fb, f);
+            collide_step3(st, fb, source_at(st, i), f);
             scatter(st, st->fmid, i, f);
         }
-    orc_wall_update(st, st->fmid);
+    wall_update(st, st->fmid, FORM_F);
 
     /* Step (4): f_hat(t+dt) = f_hat^+ - dt c_j . grad f(t+h) + dt w_j F_alpha(t)
      * + (dt^2/2) w_j d_t F_alpha(t)  (eq. 2.3.24; the last term vanishes for a
@@ -560,7 +738,9 @@ static void one_step(orc_state* st)
                                     + 0.5 * st->dt * st->dt * WJ[j] * Fa[a][i] * dm;
                 }
         }
-    orc_wall_update(st, st->fnew);
+    wall_update(st, st->fnew, FORM_HAT);
+
+    if (st->r0hat) rho0_step(st);
 
     double* t = st->fhat;
     st->fhat = st->fnew;
@@ -599,6 +779,14 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     if (p->metric && (p->inv_dx_x || p->inv_dx_y || !(p->dx_min > 0.0))) return NULL;
     if (p->force_harmonic != 0 &&
         (p->force_harmonic != 1 || !isfinite(p->force_omega) || !isfinite(p->force_phase)))
+        return NULL;
+    if (p->mass_source) {
+        if (p->pl_n != 1.0) return NULL;
+        for (size_t i = 0; i < (size_t)p->nx * p->ny; ++i)
+            if (!isfinite(p->mass_source[i])) return NULL;
+    }
+    if (p->track_rho0 != 0 &&
+        (p->track_rho0 != 1 || p->pl_n != 1.0 || p->bc_x != ORC_PERIODIC || p->bc_y != ORC_PERIODIC))
         return NULL;
 
     orc_state* st = (orc_state*)calloc(1, sizeof(orc_state));
@@ -640,6 +828,16 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
         double s = st->cs2 / p->nu; /* nu = c_s^2 / s (eq. 2.3.14) */
         orc_collision_matrices(s, p->s_ratio * s, st->dt, st->mats);
     }
+    st->R = NULL;
+    if (p->mass_source) {
+        st->R = (double*)malloc(sizeof(double) * st->n);
+        for (size_t i = 0; i < st->n; ++i) st->R[i] = p->mass_source[i];
+        for (int form = 0; form < 4; ++form) {
+            st->kap[form] = form_kappa(st, form);
+            form_inverse(st, form, st->kinv[form]);
+        }
+    }
+    st->p.mass_source = NULL;
 
     size_t bytes = sizeof(double) * NPL * st->n;
     st->fhat = (double*)malloc(bytes);
@@ -658,6 +856,22 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     orc_wall_update(st, st->fhat);
     /* walls of the intermediate fields start equal to the state */
     memcpy(st->fnew, st->fhat, bytes);
+
+    /* rho0 = 1 at rest in the velocity field: f_hat_0 = f^eq_0(1, u0) */
+    if (p->track_rho0) {
+        size_t b0 = sizeof(double) * NQ * st->n;
+        st->r0hat = (double*)malloc(b0);
+        st->r0hatp = (double*)malloc(b0);
+        st->r0barp = (double*)malloc(b0);
+        st->r0bar = (double*)malloc(b0);
+        st->r0mid = (double*)malloc(b0);
+        st->r0new = (double*)malloc(b0);
+        for (size_t i = 0; i < st->n; ++i) {
+            double fe[NQ];
+            feq_rho0(st->c, st->cs2, 1.0, u0[i], v0[i], fe);
+            for (int q = 0; q < NQ; ++q) st->r0hat[q * st->n + i] = fe[q];
+        }
+    }
     return st;
 }
 
@@ -675,6 +889,13 @@ void orc_destroy(orc_state* st)
     free(st->fbar);
     free(st->fmid);
     free(st->fnew);
+    free(st->R);
+    free(st->r0hat);
+    free(st->r0hatp);
+    free(st->r0barp);
+    free(st->r0bar);
+    free(st->r0mid);
+    free(st->r0new);
     free(st);
 }
 
@@ -696,7 +917,7 @@ void orc_moments(const orc_state* st, double* u, double* v, double* p)
     for (size_t i = 0; i < st->n; ++i) {
         double phi[NPL];
         gather(st, st->fhat, i, phi);
-        orc_node_moments(st->c, phi, &u[i], &v[i], &p[i]);
+        node_state(st, phi, FORM_HAT, source_at(st, i), &u[i], &v[i], &p[i]);
     }
 }
 
@@ -713,7 +934,7 @@ void orc_derived(const orc_state* st, double* out)
     for (size_t i = 0; i < n; ++i) {
         double fh[NPL], feq[NPL], u, v, P, scratch[125];
         gather(st, st->fhat, i, fh);
-        orc_node_moments(st->c, fh, &u, &v, &P);
+        node_state(st, fh, FORM_HAT, source_at(st, i), &u, &v, &P);
         orc_feq(st->c, u, v, P, feq);
         double nu = node_nu(st, fh, feq, st->cs2 * st->dt / 2.0);
         const double* mats = node_mats(st, nu, scratch);

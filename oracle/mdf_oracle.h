@@ -50,6 +50,13 @@ typedef struct {
      * (the inverse Jacobian in node units), or NULL.  Excludes inv_dx_x / inv_dx_y; needs
      * dx_min.  Walls, when given, lie on the index lines i = 0, nx-1 / j = 0, ny-1. */
     const double* metric;
+    /* mass source R of eq. 2.1.1 (the alpha = 0 source of eq. 2.1.2): ny*nx entries, or NULL
+     * for R = 0.  Enters the pressure of eq. 2.3.23; needs a Newtonian fluid (pl_n = 1). */
+    const double* mass_source;
+    /* 1: also advance the alpha = 0 distributions (rho0 of eq. 2.1.2), which Remark 1 says
+     * the velocity equations do not need; a check of that remark.  Periodic axes and a
+     * Newtonian fluid only.  0: not carried. */
+    int32_t track_rho0;
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -70,6 +77,8 @@ void       orc_moments(const orc_state* st, double* u, double* v, double* p);
 void       orc_derived(const orc_state* st, double* out);
 /* 8 scalars: sum u, sum v, KE, enstrophy, max|u|, max|FD div u|, non-finite count, area */
 void       orc_diagnostics(const orc_state* st, double* out);
+/* rho0 = sum_j f_hat_{j,0} at every node (ny*nx); needs track_rho0 */
+int32_t    orc_rho0(const orc_state* st, double* out);
 /* threads of the OpenMP build (no effect in the sequential build); returns the count in use */
 int32_t    orc_set_threads(int32_t n);
 
@@ -78,6 +87,11 @@ int32_t    orc_set_threads(int32_t n);
 void   orc_feq(double c, double u, double v, double P, double* out);
 /* moments of any stored form: u, v, P (eq. 2.3.23 with R = 0) */
 void   orc_node_moments(double c, const double* phi, double* u, double* v, double* P);
+/* pressure of eq. 2.3.23 with a mass source R at a node whose stored form is
+ * phi = f + kappa Lambda~ (f - f^eq) of the state's Newtonian collision matrix, by solving
+ * the definition for P; form 0: kappa = dt/2 (f_hat), 1: h/2 (f_bar), 2: -h/2 (f_bar^+),
+ * 3: 0 (f).  Returns NaN for a form outside 0..3 or a power-law state. */
+double orc_form_pressure(const orc_state* st, const double* phi, int32_t form, double R);
 /* collision matrices for rates (s, s'), time step dt (5x5, row-major):
  *   out[0]  = Lambda~                        (eq. 2.2.4 MRT matrix)
  *   out[25] = I - Lambda                     (eq. 2.2.14)

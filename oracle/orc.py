@@ -34,6 +34,8 @@ class OrcParams(C.Structure):
         ("force_x", _dp), ("force_y", _dp),
         ("force_omega", C.c_double), ("force_phase", C.c_double), ("force_harmonic", C.c_int32),
         ("metric", _dp),
+        ("mass_source", _dp),
+        ("track_rho0", C.c_int32),
     ]
 
 
@@ -100,6 +102,10 @@ def _declare(L):
         L.orc_powerlaw_nu.argtypes = [C.c_void_p, C.c_double, C.c_double]
         L.orc_set_threads.restype = C.c_int32
         L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_rho0.restype = C.c_int32
+        L.orc_rho0.argtypes = [C.c_void_p, _dp]
+        L.orc_form_pressure.restype = C.c_double
+        L.orc_form_pressure.argtypes = [C.c_void_p, _dp, C.c_int32, C.c_double]
         return L
 
 
@@ -123,11 +129,15 @@ def _params(prob):
     met = getattr(prob, "metric", None)
     met = None if met is None else np.ascontiguousarray(met, dtype=np.float64)
     assert met is None or met.shape == (4, prob.ny, prob.nx)
-    keep += [gx, gy, ffx, ffy, met]
+    rs = getattr(prob, "mass_source", None)
+    rs = None if rs is None else np.ascontiguousarray(rs, dtype=np.float64)
+    assert rs is None or rs.shape == (prob.ny, prob.nx)
+    keep += [gx, gy, ffx, ffy, met, rs]
     p = OrcParams(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                   prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
                   prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min, _ptr(ffx), _ptr(ffy),
-                  prob.force_omega, prob.force_phase, int(prob.force_harmonic), _ptr(met))
+                  prob.force_omega, prob.force_phase, int(prob.force_harmonic), _ptr(met),
+                  _ptr(rs), int(getattr(prob, "track_rho0", 0)))
     return p, keep
 
 
@@ -195,6 +205,19 @@ class Oracle:
         p = np.empty_like(u)
         self._L.orc_moments(self._h, _ptr(u), _ptr(v), _ptr(p))
         return u, v, p
+
+    def rho0(self) -> np.ndarray:
+        """rho0 of the tracked alpha = 0 equation (needs prob.track_rho0)."""
+        out = np.empty((self.ny, self.nx))
+        if self._L.orc_rho0(self._h, _ptr(out)) != 0:
+            raise ValueError("the alpha = 0 equation is not tracked in this run")
+        return out
+
+    def form_pressure(self, phi: np.ndarray, form: int, R: float) -> float:
+        """Pressure of eq. 2.3.23 with source R for one node's stored form phi (10 values)."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        assert phi.shape == (10,)
+        return self._L.orc_form_pressure(self._h, _ptr(phi), int(form), float(R))
 
     def derived(self) -> np.ndarray:
         out = np.empty((14, self.ny, self.nx))

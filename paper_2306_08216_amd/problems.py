@@ -60,6 +60,8 @@ class Problem:
     force_phase: float = 0.0
     metric: Optional[np.ndarray] = None    # (4, ny, nx): d i/dx, d i/dy, d j/dx, d j/dy (general mapping)
     node_xy: Optional[tuple] = None        # physical node positions (X, Y) of a general mapping
+    mass_source: Optional[np.ndarray] = None  # (ny, nx) mass source R of eq. 2.1.1 (None: R = 0)
+    track_rho0: bool = False               # oracle only: also advance the alpha = 0 equation
     name: str = ""
 
     @property
@@ -139,6 +141,60 @@ def four_roll_mill_exact(prob: Problem, u0: float = 1e-4):
     c, ss = u0 * np.cos(X) * np.cos(Y), u0 * np.sin(X) * np.sin(Y)
     return {"u": u0 * np.sin(X) * np.cos(Y), "v": -u0 * np.sin(Y) * np.cos(X), "ux": c, "uy": -ss,
             "vx": ss, "vy": -c, "Sxx": c, "Sxy": 0.0 * c, "Syy": -c, "omega": 2.0 * ss, "Omega_xy": -ss}
+
+
+def divergent_flow(n: int = 32, u0: float = 0.01, nu: float = 0.02, cfl: float = 0.5, eta: float = 0.8,
+                   s_ratio: float = 1.5, start: str = "exact") -> Problem:
+    """A steady flow with a mass source on the periodic [0, 2pi]^2: u = U0 sin x,
+    v = U0 sin y has divergence R = U0 (cos x + cos y) (eq. 2.1.1), and with the
+    uniform pressure it is a steady solution of eq. 2.1.2 under the force
+        F_x = d(u u)/dx + d(u v)/dy - nu lap u = U0^2 (sin 2x + sin x cos y) + nu U0 sin x,
+        F_y = d(v u)/dx + d(v v)/dy - nu lap v = U0^2 (sin 2y + sin y cos x) + nu U0 sin y.
+    A manufactured case: the paper gives none with R != 0.  start: "exact" or "rest"."""
+    L = 2.0 * math.pi
+    x = _axis_nodes(n, L, PERIODIC)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    fx = u0 * u0 * (np.sin(2.0 * X) + np.sin(X) * np.cos(Y)) + nu * u0 * np.sin(X)
+    fy = u0 * u0 * (np.sin(2.0 * Y) + np.sin(Y) * np.cos(X)) + nu * u0 * np.sin(Y)
+    if start == "exact":
+        u, v = u0 * np.sin(X), u0 * np.sin(Y)
+    else:
+        u, v = np.zeros((n, n)), np.zeros((n, n))
+    return Problem(nx=n, ny=n, lx=L, ly=L, nu=nu, u0=u, v0=v, p0=np.zeros((n, n)), cfl=cfl, eta=eta,
+                   s_ratio=s_ratio, force_x=fx, force_y=fy, mass_source=u0 * (np.cos(X) + np.cos(Y)),
+                   name=f"divergent_flow_{n}")
+
+
+def divergent_flow_exact(prob: Problem, u0: float = 0.01):
+    """u, v, du/dx, dv/dy and the divergence of divergent_flow at the nodes."""
+    X, Y = np.meshgrid(prob.node_x(), prob.node_y(), indexing="xy")
+    return {"u": u0 * np.sin(X), "v": u0 * np.sin(Y), "ux": u0 * np.cos(X), "vy": u0 * np.cos(Y),
+            "div": u0 * (np.cos(X) + np.cos(Y))}
+
+
+def divergent_channel(n: int = 32, v0: float = 0.01, nu: float = 0.02, cfl: float = 0.5, eta: float = 0.8,
+                      s_ratio: float = 1.5, start: str = "exact") -> Problem:
+    """A channel on [0, 1]^2, periodic in x with walls at y = 0 and 1, fed by a
+    mass source: u = 0, v = V0 sin(pi y) vanishes on both walls and has
+    divergence R = pi V0 cos(pi y) (eq. 2.1.1); with uniform pressure it is a
+    steady solution of eq. 2.1.2 under F_x = 0 and
+        F_y = d(v v)/dy - nu d2v/dy2 = pi V0^2 sin(2 pi y) + nu pi^2 V0 sin(pi y).
+    A manufactured case with walls.  start: "exact" or "rest"."""
+    x = _axis_nodes(n, 1.0, PERIODIC)
+    y = _axis_nodes(n, 1.0, WALL)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    fy = math.pi * v0 * v0 * np.sin(2.0 * math.pi * Y) + nu * math.pi ** 2 * v0 * np.sin(math.pi * Y)
+    z = np.zeros((n, n))
+    v = v0 * np.sin(math.pi * Y) if start == "exact" else z.copy()
+    return Problem(nx=n, ny=n, lx=1.0, ly=1.0, nu=nu, u0=z, v0=v, p0=z.copy(), cfl=cfl, eta=eta,
+                   s_ratio=s_ratio, bc_x=PERIODIC, bc_y=WALL, force_x=z.copy(), force_y=fy,
+                   mass_source=math.pi * v0 * np.cos(math.pi * Y), name=f"divergent_channel_{n}")
+
+
+def divergent_channel_exact(prob: Problem, v0: float = 0.01):
+    """u, v of divergent_channel at the nodes."""
+    X, Y = np.meshgrid(prob.node_x(), prob.node_y(), indexing="xy")
+    return {"u": 0.0 * X, "v": v0 * np.sin(math.pi * Y)}
 
 
 def swept_vortex(n: int = 32, u0: float = 0.01, nu: float = 0.01, f0: float = 1e-3, omega: float = 0.2,

@@ -103,6 +103,19 @@ CASES = [
      "st->Fy[i] = p->fy + (p->force_y ? p->force_y[i] : 0.0);",
      "st->Fy[i] = p->fy + (p->force_x ? p->force_x[i] : 0.0);",
      "test_oracle_forced", "test_four_roll_mill_steady_solution"),
+    ("pressure of eq. 2.3.23 without the mass source term",
+     "r[k] = Ptry - 0.5 * (T + st->p.nu * R - (u * u + v * v));", "r[k] = Ptry - 0.5 * (T - (u * u + v * v));",
+     "test_oracle_source", "test_divergent_flow_converges_to_its_closed_form"),
+    ("f_hat taken with the kappa of f_bar in the pressure solve",
+     "return form == FORM_HAT ? 0.5 * st->dt :", "return form == FORM_HAT ? 0.5 * st->h :",
+     "test_oracle_source", "test_form_pressure_inverts_the_stored_forms"),
+    ("alpha = 0 equation without its source in Step (4)",
+     "+ st->dt * WJ[q] * source_at(st, i);", ";",
+     "test_oracle_source", "test_rho0_equation_stays_uniform"),
+    ("wall rule taking the neighbour pressures without the mass source",
+     "node_state(st, ph1, form, source_at(st, i1), &u1, &v1, &P1);",
+     "node_state(st, ph1, form, 0.0, &u1, &v1, &P1);",
+     "test_oracle_source", "test_divergent_channel_with_walls"),
 ]
 
 
