@@ -87,11 +87,18 @@ typedef struct {
      * values must be finite with a non-zero Jacobian.  Runs on the three-pass step (variant 0)
      * only; batches and the closure take no general mapping. */
     const double* metric;
+    /* HOST, ny*nx values (x fastest), or NULL for R = 0: the mass source R of eq. 2.1.1 (the
+     * alpha = 0 source of eq. 2.1.2), steady.  It enters the pressure of eq. 2.3.23, which on the
+     * stored distributions phi = f + kappa Lambda~ (f - f^eq) becomes the plain sum plus
+     * R (nu + kappa c_s^2)/2; the alpha = 0 equation itself is not carried (Remark 1).  Needs a
+     * Newtonian fluid (pl_n = 1) and finite values; runs on the three-pass step (variant 0) only;
+     * batches take none. */
+    const double* mass_source;
 } mdf_params;
 
 /* Bytes of device workspace a context for these parameters needs, or 0 if the
  * parameters are invalid.  Depends only on nx, ny and whether a force field
- * (force_x or force_y) is given. */
+ * (force_x or force_y), a general mapping (metric) or a mass source is given. */
 size_t mdf_workspace_size(const mdf_params* p);
 
 /* Create a context and initialise the state f_hat = f^eq(u0, v0, p0) of
@@ -107,8 +114,9 @@ size_t mdf_workspace_size(const mdf_params* p);
  * cfl <= 0, c <= 0, eta outside [0,1], an axis has fewer than 5 or more than
  * 32768 nodes, pl_n is
  * not 1, 0.5 or 1.5, the power-law clamp is empty, metrics come without dx_min,
- * a metric or force value is not finite, or the workspace is too small or
- * misaligned.  The metric and force arrays are copied; p may be freed after. */
+ * a metric, force or mass-source value is not finite, a mass source comes with
+ * a power-law fluid, or the workspace is too small or misaligned.  The metric,
+ * force and mass-source arrays are copied; p may be freed after. */
 mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0,
                     void* workspace, size_t ws_bytes, void* hip_stream, mdf_ctx** out);
 
@@ -117,8 +125,9 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
  * (eq. 2.3.24), with the mixed difference of eqs. 2.2.12-2.2.13.  n >= 0. */
 mdf_status mdf_step(mdf_ctx* ctx, int64_t n);
 
-/* Velocity and pressure of the current state (eqs. 2.3.4 and 2.3.23 with R = 0)
- * into caller-owned DEVICE fields (ny*nx each); any pointer may be NULL. */
+/* Velocity and pressure of the current state (eqs. 2.3.4 and 2.3.23, with the
+ * run's mass source R, zero without one) into caller-owned DEVICE fields (ny*nx
+ * each); any pointer may be NULL. */
 mdf_status mdf_moments(mdf_ctx* ctx, double* u, double* v, double* p);
 
 /* Local quantities from the first moment of the non-equilibrium part
@@ -162,7 +171,8 @@ mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, cons
  * segments next to walls, whose rows cost more; seg_h < -4 is MDF_EINVAL.
  * Changing the variant or the shape rebuilds that partition (a short
  * synchronous upload on the context's stream).  Results agree to rounding
- * whatever the choice. */
+ * whatever the choice.  A general mapping or a mass source has variant 0 only
+ * (MDF_EINVAL for any other). */
 mdf_status mdf_set_kernel(mdf_ctx* ctx, int32_t variant, int32_t tile_w, int32_t seg_h, int32_t prefetch);
 
 /* Scalings (0..10) of the measured extra per-row cost of segments next to
@@ -172,8 +182,8 @@ mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_w
 
 /* Autotuner for this context: times every fused kernel (variant 1 with
  * tile_w 64, 128 and 256, and variant 2 for a Newtonian fluid; only variant 1
- * with tile_w 64 and prefetch 2 under a force field; a general mapping has
- * only variant 0, which it reports without timing), prefetch
+ * with tile_w 64 and prefetch 2 under a force field; a general mapping or a
+ * mass source has only variant 0, which it reports without timing), prefetch
  * depth (2, 3) and eight scalings (0.3..3.5) of the
  * wall-row cost factors of the one-round balanced partition over `steps`
  * steps of the run itself, times the three fastest again over 4 x `steps`

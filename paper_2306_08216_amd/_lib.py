@@ -34,6 +34,7 @@ class mdf_params(C.Structure):
         ("force_x", _dp), ("force_y", _dp),
         ("force_omega", C.c_double), ("force_phase", C.c_double), ("force_harmonic", C.c_int32),
         ("metric", _dp),
+        ("mass_source", _dp),
     ]
 
 

@@ -64,7 +64,8 @@ mdf_status hip_check(mdf_ctx* c, hipError_t e, const char* what)
 
 struct Layout {
     size_t pitch;                 // nodes per row
-    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, off_seg, off_ff, off_met, total;  // bytes
+    size_t off_f0, off_f1, off_fbp, off_fmid, off_gx, off_gy, off_dp, off_do, off_seg, off_ff, off_met, off_rs,
+        total;  // bytes
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -73,7 +74,7 @@ constexpr int kSegCap = 4096;   // entries of the segment table (one per workgro
 
 bool has_force_field(const mdf_params* p) { return p->force_x != nullptr || p->force_y != nullptr; }
 
-Layout layout_for(int nx, int ny, bool force_field, bool metric)
+Layout layout_for(int nx, int ny, bool force_field, bool metric, bool source)
 {
     Layout L;
     // rows of 80 bytes per node (x-part block, then y-part block); 16-node multiples keep
@@ -94,6 +95,8 @@ Layout layout_for(int nx, int ny, bool force_field, bool metric)
     L.off_ff = o;   o += force_field ? align256(2 * L.pitch * (size_t)ny * sizeof(double)) : 0;
     // general mapping: 4 planes of nx*ny metric values
     L.off_met = o;  o += metric ? align256(4 * (size_t)nx * (size_t)ny * sizeof(double)) : 0;
+    // mass source: one plane of nx*ny values
+    L.off_rs = o;   o += source ? align256((size_t)nx * (size_t)ny * sizeof(double)) : 0;
     L.total = o;
     return L;
 }
@@ -120,7 +123,13 @@ const char* validate(const mdf_params* p)
         return "non-finite force_omega or force_phase";
     if (p->metric && (p->inv_dx_x || p->inv_dx_y)) return "a general mapping (metric) excludes inv_dx_x and inv_dx_y";
     if (p->metric && !(p->dx_min > 0.0)) return "a general mapping needs dx_min > 0";
+    if (p->mass_source && p->pl_n != 1.0) return "a mass source needs a Newtonian fluid (pl_n = 1)";
     return nullptr;
+}
+
+Layout layout_of(const mdf_params* p)
+{
+    return layout_for(p->nx, p->ny, has_force_field(p), p->metric != nullptr, p->mass_source != nullptr);
 }
 
 // Force terms of the step that starts at time t = step * dt for a force
@@ -206,6 +215,14 @@ StepConsts make_consts(const mdf_params& p, const Layout& L)
     K.dw = K.dt * K.w;
     K.ff = nullptr;
     K.met = nullptr;
+    // pressure offsets per unit mass source of the stored forms (eq. 2.3.23
+    // with c_s^2/s = nu): R (nu + kappa c_s^2)/2 for f_hat (kappa = dt/2),
+    // f_bar (h/2), f_bar^+ (-h/2) and f (0)
+    K.rsrc = nullptr;
+    K.r_hat = 0.5 * (p.nu + 0.5 * K.dt * K.cs2);
+    K.r_bar = 0.5 * (p.nu + 0.5 * K.h * K.cs2);
+    K.r_bp = 0.5 * (p.nu - 0.5 * K.h * K.cs2);
+    K.r_f = 0.5 * p.nu;
     return K;
 }
 
@@ -395,6 +412,7 @@ const char* validate_batch(const mdf_params* ps, int count)
         if (has_force_field(&ps[i])) return "batched instances take a uniform force only";
         if (ps[i].force_harmonic) return "batched instances take a steady force only";
         if (ps[i].metric) return "batched instances take no general mapping";
+        if (ps[i].mass_source) return "batched instances take no mass source";
         if (ps[i].pl_n != ps[0].pl_n) return "batched instances must share the fluid model (pl_n)";
     }
     return nullptr;
@@ -486,7 +504,7 @@ extern "C" {
 size_t mdf_workspace_size(const mdf_params* p)
 {
     if (validate(p)) return 0;
-    return layout_for(p->nx, p->ny, has_force_field(p), p->metric != nullptr).total;
+    return layout_of(p).total;
 }
 
 mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, const double* p0, void* workspace,
@@ -496,7 +514,7 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     *out = nullptr;
     if (const char* why = validate(p)) return fail(nullptr, MDF_EINVAL, "%s", why);
     if (!u0 || !v0 || !p0) return fail(nullptr, MDF_EINVAL, "initial fields must be non-NULL device pointers");
-    const Layout L = layout_for(p->nx, p->ny, has_force_field(p), p->metric != nullptr);
+    const Layout L = layout_of(p);
     if (!workspace || ws_bytes < L.total)
         return fail(nullptr, MDF_EINVAL, "workspace too small: need %zu bytes, got %zu", L.total, ws_bytes);
     if (((uintptr_t)workspace & 255u) != 0) return fail(nullptr, MDF_EINVAL, "workspace must be 256-byte aligned");
@@ -509,6 +527,7 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     c->p.force_x = nullptr;
     c->p.force_y = nullptr;
     c->p.metric = nullptr;
+    c->p.mass_source = nullptr;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char*)workspace;
     c->ws_bytes = ws_bytes;
@@ -535,7 +554,8 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     // allows, and there one wave per strip is faster.  A force field has
     // kernels of the second kind only.
     c->variant = (p->pl_n == 1.0 && !has_force_field(p)) ? 2 : 1;
-    if (p->metric) c->variant = 0;   // a general mapping runs on the three-pass step
+    // a general mapping and a mass source run on the three-pass step
+    if (p->metric || p->mass_source) c->variant = 0;
 
     // derivative scales 1/(X' dxi) per node (uniform: 1/dx)
     std::string hbuf;
@@ -617,6 +637,24 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
             return s;
         }
         c->K.met = dmet;
+    }
+    // mass source: one finite value per node
+    if (p->mass_source) {
+        const size_t n = (size_t)p->nx * p->ny;
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(p->mass_source[i])) {
+                delete c;
+                return fail(nullptr, MDF_EINVAL, "mass source values must be finite");
+            }
+        double* drs = (double*)(c->ws + L.off_rs);
+        hipError_t e = hipMemcpyAsync(drs, p->mass_source, sizeof(double) * n, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            mdf_status s = hip_check(nullptr, e, "mass source upload");
+            delete c;
+            return s;
+        }
+        c->K.rsrc = drs;
     }
     {
         const mdf_status s = prepare_shape(c);
@@ -720,6 +758,7 @@ mdf_status mdf_set_kernel(mdf_ctx* c, int32_t variant, int32_t tile_w, int32_t s
     if (variant < 0 || variant > 2) return fail(c, MDF_EINVAL, "variant must be 0, 1 or 2");
     if (variant == 2 && c->K.ff) return fail(c, MDF_EINVAL, "a force field runs on variant 0 or 1 only");
     if (variant != 0 && c->K.met) return fail(c, MDF_EINVAL, "a general mapping runs on variant 0 only");
+    if (variant != 0 && c->K.rsrc) return fail(c, MDF_EINVAL, "a mass source runs on variant 0 only");
     if (seg_h < -4) return fail(c, MDF_EINVAL, "seg_h below 0 selects 1 to 4 rounds of the balanced table");
     mdf::FusedShape sh = c->shape;
     int rounds = c->rounds;
@@ -792,7 +831,7 @@ mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
     if (steps < 1) return fail(c, MDF_EINVAL, "steps must be >= 1");
-    if (c->K.met) {   // a general mapping has one step kernel: nothing to choose
+    if (c->K.met || c->K.rsrc) {   // one step kernel (the three-pass step): nothing to choose
         if (choice) {
             const double ch[6] = {0.0, (double)c->shape.prefetch, c->cx_scale, c->cy_scale, 0.0, (double)c->shape.tile_w};
             for (int k = 0; k < 6; ++k) choice[k] = ch[k];

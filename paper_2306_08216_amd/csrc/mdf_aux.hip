@@ -120,7 +120,10 @@ __global__ void k_wall_fix(StepConsts K, double* __restrict__ f)
     double p1[10], p2[10], out[10];
     load10(K, f, x1, y1, p1);
     load10(K, f, x2, y2, p2);
-    wall_extrapolate(K, p1, p2, uw, out);
+    if (K.rsrc)
+        wall_extrapolate<true>(K, p1, p2, uw, out, K.r_hat * source_at(K, x1, y1), K.r_hat * source_at(K, x2, y2));
+    else
+        wall_extrapolate(K, p1, p2, uw, out);
     store10(K, f, x, y, out);
 }
 
@@ -132,19 +135,21 @@ __global__ void k_moments(StepConsts K, const double* __restrict__ f, double* __
     double phi[10], uu, vv, PP;
     load10(K, f, x, y, phi);
     node_moments(phi, K.c, uu, vv, PP);
+    if (K.rsrc) PP += K.r_hat * source_at(K, x, y);
     const long long s = (long long)y * K.nx + x;
     if (u) u[s] = uu;
     if (v) v[s] = vv;
     if (p) p[s] = PP;
 }
 
-// Local derived quantities (Sec. 2.4) at one node: out[14] in the list order of mdf.h.
+// Local derived quantities (Sec. 2.4) at node (x, y): out[14] in the list order of mdf.h.
 // M(f - f^eq) = M(f_hat - f^eq)/(1 + s dt/2), so eq. 2.4.1 reads
 // grad_b u_a = -sum_j c_{j,b} (f_hat - f^eq)_{j,a} / (nu + c_s^2 dt/2).
-__device__ __forceinline__ void derived_node(const StepConsts& K, const double* fh, double* out)
+__device__ __forceinline__ void derived_node(const StepConsts& K, const double* fh, int x, int y, double* out)
 {
     double u, v, P, fe[10];
     node_moments(fh, K.c, u, v, P);
+    if (K.rsrc) P += K.r_hat * source_at(K, x, y);
     equilibrium(u, v, P, K, fe);
     const double nu = K.pl == PL_NEWTON ? K.nu : powerlaw_nu_sq(K, noneq_shear_sq(fh, fe, K.c), K.theta1);
     const double inv = -K.c / (nu + K.theta1);
@@ -175,7 +180,7 @@ __global__ void k_derived(StepConsts K, const double* __restrict__ f, double* __
     if (x >= K.nx || y >= K.ny) return;
     double fh[10], d[14];
     load10(K, f, x, y, fh);
-    derived_node(K, fh, d);
+    derived_node(K, fh, x, y, d);
     const long long n = (long long)K.nx * K.ny, s = (long long)y * K.nx + x;
     int slot = 0;
 #pragma unroll
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
         double fh[10], d[14], u, v, P;
         load10(K, f, x, y, fh);
         node_moments(fh, K.c, u, v, P);
-        derived_node(K, fh, d);
+        derived_node(K, fh, x, y, d);
         double dA = 1.0 / (gx_at(K, x) * gy_at(K, y));
         const size_t nn = (size_t)K.nx * K.ny, ii = (size_t)y * K.nx + x;
         if (K.met) dA = 1.0 / fabs(K.met[ii] * K.met[3 * nn + ii] - K.met[nn + ii] * K.met[2 * nn + ii]);
@@ -338,7 +343,16 @@ inline int perimeter_count(const StepConsts& K)
 
 // ---- three-pass reference step ----
 
+// pressure offset of a stored form with coefficient r at node (x, y): SRC only
+template <bool SRC>
+__device__ __forceinline__ double src_dp(const StepConsts& K, double r, int x, int y)
+{
+    if constexpr (SRC) return r * source_at(K, x, y);
+    return 0.0;
+}
+
 // pass A: f_bar^+ at every node (Step (1), eq. 2.2.15); wall nodes by the wall rule
+template <bool SRC>
 __global__ __launch_bounds__(256) void k_pass_a(StepConsts K, const double* __restrict__ fh, double* __restrict__ fbp)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -348,31 +362,33 @@ __global__ __launch_bounds__(256) void k_pass_a(StepConsts K, const double* __re
     if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
         double b[10], p1[10], p2[10];
         load10(K, fh, x1, y1, a);
-        collide1_bar(K, a, p1);
+        collide1_bar<SRC>(K, a, p1, src_dp<SRC>(K, K.r_hat, x1, y1));
         load10(K, fh, x2, y2, b);
-        collide1_bar(K, b, p2);
-        wall_extrapolate(K, p1, p2, uw, out);
+        collide1_bar<SRC>(K, b, p2, src_dp<SRC>(K, K.r_hat, x2, y2));
+        wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, K.r_bp, x1, y1), src_dp<SRC>(K, K.r_bp, x2, y2));
     } else {
         load10(K, fh, x, y, a);
-        collide1_bar(K, a, out);
+        collide1_bar<SRC>(K, a, out, src_dp<SRC>(K, K.r_hat, x, y));
     }
     store10(K, fbp, x, y, out);
 }
 
 // f(t+h) at an interior node: half step (eq. 2.3.25 in Taylor form) then Step (3)
+template <bool SRC>
 __device__ __forceinline__ void mid_at(const StepConsts& K, const double* fbp, int x, int y, double* f)
 {
     double fb[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k)
         fb[k] = comp(K, fbp, x, y, k) - transport_at(K, fbp, k, x, y, K.lam_h) + hwf_at(K, x, y, k / 5);
-    collide3(K, fb, f);
+    collide3<SRC>(K, fb, f, src_dp<SRC>(K, K.r_bar, x, y));
 }
 
 // Wall nodes (one thread per perimeter node; the interior is k_pass_tiled):
 // a wall node extrapolates from its two inward neighbours, and one loop over
 // them keeps a single inlined copy of the node update (three copies spilled
 // to scratch).
+template <bool SRC>
 __global__ __launch_bounds__(256) void k_pass_b(StepConsts K, const double* __restrict__ fbp,
                                                 double* __restrict__ fmid)
 {
@@ -385,7 +401,7 @@ __global__ __launch_bounds__(256) void k_pass_b(StepConsts K, const double* __re
 #pragma nounroll
     for (int t = 0; t < cnt; ++t) {
         double v[10];
-        mid_at(K, fbp, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
+        mid_at<SRC>(K, fbp, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
             if (t == 0) p1[k] = v[k];
@@ -394,7 +410,7 @@ __global__ __launch_bounds__(256) void k_pass_b(StepConsts K, const double* __re
     }
     if (wall) {
         double out[10];
-        wall_extrapolate(K, p1, p2, uw, out);
+        wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, K.r_f, x1, y1), src_dp<SRC>(K, K.r_f, x2, y2));
         store10(K, fmid, x, y, out);
     } else {
         store10(K, fmid, x, y, p1);
@@ -402,16 +418,18 @@ __global__ __launch_bounds__(256) void k_pass_b(StepConsts K, const double* __re
 }
 
 // f_hat(t+dt) at an interior node: Step (4), eq. 2.3.24
+template <bool SRC>
 __device__ __forceinline__ void full_at(const StepConsts& K, const double* fh, const double* fmid, int x, int y,
                                         double* out)
 {
     double a[10], fhp[10];
     load10(K, fh, x, y, a);
-    collide1_hat(K, a, fhp);
+    collide1_hat<SRC>(K, a, fhp, src_dp<SRC>(K, K.r_hat, x, y));
 #pragma unroll
     for (int k = 0; k < 10; ++k) out[k] = fhp[k] - transport_at(K, fmid, k, x, y, K.lam_dt) + dwf_at(K, x, y, k / 5);
 }
 
+template <bool SRC>
 __global__ __launch_bounds__(256) void k_pass_c(StepConsts K, const double* __restrict__ fh,
                                                 const double* __restrict__ fmid, double* __restrict__ fnew)
 {
@@ -424,7 +442,7 @@ __global__ __launch_bounds__(256) void k_pass_c(StepConsts K, const double* __re
 #pragma nounroll
     for (int t = 0; t < cnt; ++t) {
         double v[10];
-        full_at(K, fh, fmid, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
+        full_at<SRC>(K, fh, fmid, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
             if (t == 0) p1[k] = v[k];
@@ -433,7 +451,7 @@ __global__ __launch_bounds__(256) void k_pass_c(StepConsts K, const double* __re
     }
     if (wall) {
         double out[10];
-        wall_extrapolate(K, p1, p2, uw, out);
+        wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, K.r_hat, x1, y1), src_dp<SRC>(K, K.r_hat, x2, y2));
         store10(K, fnew, x, y, out);
     } else {
         store10(K, fnew, x, y, p1);
@@ -509,7 +527,7 @@ __device__ __forceinline__ double transport_tile(const StepConsts& K, const doub
 
 // FULL = false: pass B (half step of f_bar^+, then Step (3)) into f(t+h);
 // FULL = true: pass C (Step (4) on f(t+h) with f_hat^+ recomputed from f_hat).
-template <bool FULL>
+template <bool FULL, bool SRC>
 __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const double* __restrict__ src,
                                                            const double* __restrict__ fh, double* __restrict__ dst)
 {
@@ -531,7 +549,7 @@ __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const d
     if (FULL) {
         double a[10];
         load_node(fh, K.pitch, x, y, a);
-        collide1_hat(K, a, base);
+        collide1_hat<SRC>(K, a, base, src_dp<SRC>(K, K.r_hat, x, y));
     } else {
 #pragma unroll
         for (int q = 0; q < 10; ++q) base[q] = tile[q][cy][cx];
@@ -545,7 +563,7 @@ __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const d
         store_node(dst, K.pitch, x, y, out);
     } else {
         double fm[10];
-        collide3(K, out, fm);
+        collide3<SRC>(K, out, fm, src_dp<SRC>(K, K.r_bar, x, y));
         store_node(dst, K.pitch, x, y, fm);
     }
 }
@@ -642,16 +660,29 @@ hipError_t launch_unpack(const StepConsts& K, const double* dense, double* f, hi
     return hipGetLastError();
 }
 
-hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew,
-                             hipStream_t s)
+namespace {
+template <bool SRC>
+void three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew, hipStream_t s)
 {
     const dim3 b(64, 4), bt(TB_X, TB_Y);
     const int nper = perimeter_count(K);
-    hipLaunchKernelGGL(k_pass_a, grid2d(K, b), b, 0, s, K, fh, fbp);
-    hipLaunchKernelGGL(k_pass_tiled<false>, grid2d(K, bt), bt, 0, s, K, fbp, nullptr, fmid);
-    if (nper > 0) hipLaunchKernelGGL(k_pass_b, dim3((nper + 255) / 256), dim3(256), 0, s, K, fbp, fmid);
-    hipLaunchKernelGGL(k_pass_tiled<true>, grid2d(K, bt), bt, 0, s, K, fmid, fh, fnew);
-    if (nper > 0) hipLaunchKernelGGL(k_pass_c, dim3((nper + 255) / 256), dim3(256), 0, s, K, fh, fmid, fnew);
+    hipLaunchKernelGGL(k_pass_a<SRC>, grid2d(K, b), b, 0, s, K, fh, fbp);
+    hipLaunchKernelGGL((k_pass_tiled<false, SRC>), grid2d(K, bt), bt, 0, s, K, fbp, nullptr, fmid);
+    if (nper > 0) hipLaunchKernelGGL(k_pass_b<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fbp, fmid);
+    hipLaunchKernelGGL((k_pass_tiled<true, SRC>), grid2d(K, bt), bt, 0, s, K, fmid, fh, fnew);
+    if (nper > 0) hipLaunchKernelGGL(k_pass_c<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fh, fmid, fnew);
+}
+}  // namespace
+
+// the kernels with the mass source's pressure offsets are separate instances,
+// so a run without source executes exactly the plain step
+hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew,
+                             hipStream_t s)
+{
+    if (K.rsrc)
+        three_pass<true>(K, fh, fbp, fmid, fnew, s);
+    else
+        three_pass<false>(K, fh, fbp, fmid, fnew, s);
     return hipGetLastError();
 }
 

@@ -54,6 +54,14 @@ struct StepConsts {
     // general mapping: 4 planes of nx*ny (d i/dx, d i/dy, d j/dx, d j/dy per node), or null
     const double* met;
     double hw, dw;
+    // mass source R of eq. 2.1.1: nx*ny values (row y at y*nx), or null for R = 0.
+    // The pressure of eq. 2.3.23 is defined on f; a stored form phi = f + kappa
+    // Lambda~ (f - f^eq) has the first-moment trace of f shifted by kappa c_s^2 R
+    // (the collision scales first moments by s and s nu = c_s^2), so its pressure
+    // is the plain sum of node_moments plus R (nu + kappa c_s^2)/2.  Per unit R:
+    // r_hat (f_hat, kappa = dt/2), r_bar (f_bar, h/2), r_bp (f_bar^+, -h/2), r_f (f).
+    const double* rsrc;
+    double r_hat, r_bar, r_bp, r_f;
 };
 
 // State layout (row-split).  Row y occupies 80*pitch contiguous bytes: first
@@ -375,61 +383,79 @@ __device__ __forceinline__ Relax step3_factors(const StepConsts& K, const double
     return step3_factors_t<PL_THREE_HALVES>(K, fb, fe);
 }
 
+// The node-level updates below take the pressure offset dP of a mass source
+// (R times the stored form's coefficient in StepConsts) when SRC is set; with
+// SRC unset they are the plain updates of a run without source.
+template <bool SRC>
+__device__ __forceinline__ void moments_equilibrium(const StepConsts& K, const double* phi, double dP, double& u,
+                                                    double& v, double& P, double* fe)
+{
+    node_moments(phi, K.c, u, v, P);
+    if constexpr (SRC) P += dP;
+    equilibrium(u, v, P, K, fe);
+}
+
 // Step (1): f_hat -> f_hat^+ (eq. 2.2.14) and f_bar^+ (eq. 2.2.15).
-__device__ __forceinline__ void collide1(const StepConsts& K, const double* fh, double* fhp, double* fbp)
+template <bool SRC = false>
+__device__ __forceinline__ void collide1(const StepConsts& K, const double* fh, double* fhp, double* fbp,
+                                         double dP = 0.0)
 {
     double u, v, P, fe[10];
-    node_moments(fh, K.c, u, v, P);
-    equilibrium(u, v, P, K, fe);
+    moments_equilibrium<SRC>(K, fh, dP, u, v, P, fe);
     Relax ra, rb;
     step1_factors(K, fh, fe, ra, rb);
     relax(fh, fe, ra, fhp);
     relax(fh, fe, rb, fbp);
 }
 
-__device__ __forceinline__ void collide1_bar(const StepConsts& K, const double* fh, double* fbp)
+template <bool SRC = false>
+__device__ __forceinline__ void collide1_bar(const StepConsts& K, const double* fh, double* fbp, double dP = 0.0)
 {
     double u, v, P, fe[10];
-    node_moments(fh, K.c, u, v, P);
-    equilibrium(u, v, P, K, fe);
+    moments_equilibrium<SRC>(K, fh, dP, u, v, P, fe);
     Relax ra, rb;
     step1_factors(K, fh, fe, ra, rb);
     relax(fh, fe, rb, fbp);
 }
 
-__device__ __forceinline__ void collide1_hat(const StepConsts& K, const double* fh, double* fhp)
+template <bool SRC = false>
+__device__ __forceinline__ void collide1_hat(const StepConsts& K, const double* fh, double* fhp, double dP = 0.0)
 {
     double u, v, P, fe[10];
-    node_moments(fh, K.c, u, v, P);
-    equilibrium(u, v, P, K, fe);
+    moments_equilibrium<SRC>(K, fh, dP, u, v, P, fe);
     Relax ra, rb;
     step1_factors(K, fh, fe, ra, rb);
     relax(fh, fe, ra, fhp);
 }
 
 // Step (3): f(t+h) = f^eq + R_q(f_bar - f^eq) (eq. 2.2.16).
-__device__ __forceinline__ void collide3(const StepConsts& K, const double* fb, double* f)
+template <bool SRC = false>
+__device__ __forceinline__ void collide3(const StepConsts& K, const double* fb, double* f, double dP = 0.0)
 {
     double u, v, P, fe[10];
-    node_moments(fb, K.c, u, v, P);
-    equilibrium(u, v, P, K, fe);
+    moments_equilibrium<SRC>(K, fb, dP, u, v, P, fe);
     const Relax rq = step3_factors(K, fb, fe);
     relax(fb, fe, rq, f);
 }
 
 // Wall rule: Pi(w) = f^eq(u_w, P_1) + 2 [Pi(1) - f^eq(1)] - [Pi(2) - f^eq(2)]
-// for the components listed in `mask` (bit k = plane k).
+// (dP1, dP2: the pressure offsets of a mass source at the two neighbours).
+template <bool SRC = false>
 __device__ __forceinline__ void wall_extrapolate(const StepConsts& K, const double* p1, const double* p2, double uw,
-                                                 double* out)
+                                                 double* out, double dP1 = 0.0, double dP2 = 0.0)
 {
     double u1, v1, P1, u2, v2, P2, e1[10], e2[10], ew[10];
-    node_moments(p1, K.c, u1, v1, P1);
-    node_moments(p2, K.c, u2, v2, P2);
-    equilibrium(u1, v1, P1, K, e1);
-    equilibrium(u2, v2, P2, K, e2);
+    moments_equilibrium<SRC>(K, p1, dP1, u1, v1, P1, e1);
+    moments_equilibrium<SRC>(K, p2, dP2, u2, v2, P2, e2);
     equilibrium(uw, 0.0, P1, K, ew);
 #pragma unroll
     for (int k = 0; k < 10; ++k) out[k] = ew[k] + 2.0 * (p1[k] - e1[k]) - (p2[k] - e2[k]);
+}
+
+// mass source at node (x, y) (StepConsts::rsrc must be set)
+__device__ __forceinline__ double source_at(const StepConsts& K, int x, int y)
+{
+    return K.rsrc[(size_t)y * K.nx + x];
 }
 
 // tau c_j . grad Pi for the velocity of sign sg along one axis with the mixed

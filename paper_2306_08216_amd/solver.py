@@ -35,11 +35,13 @@ def params_of(prob: Problem, keep: list) -> L.mdf_params:
             raise ValueError("force fields must have shape (ny, nx)")
     if prob.metric is not None and np.shape(prob.metric) != (4, prob.ny, prob.nx):
         raise ValueError("a general mapping's metric must have shape (4, ny, nx)")
+    if prob.mass_source is not None and np.shape(prob.mass_source) != (prob.ny, prob.nx):
+        raise ValueError("a mass source must have shape (ny, nx)")
     return L.mdf_params(prob.nx, prob.ny, prob.lx, prob.ly, prob.nu, prob.pl_n, prob.nu_min, prob.nu_max,
                         prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
                         prob.fx, prob.fy, arr(prob.inv_dx_x), arr(prob.inv_dx_y), prob.dx_min,
                         arr(prob.force_x), arr(prob.force_y), prob.force_omega, prob.force_phase,
-                        int(prob.force_harmonic), arr(prob.metric))
+                        int(prob.force_harmonic), arr(prob.metric), arr(prob.mass_source))
 
 
 class Solver:

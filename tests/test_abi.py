@@ -55,9 +55,13 @@ def test_workspace_size_and_validation(L):
                 dict(force_harmonic=2), dict(force_harmonic=True, force_omega=float("nan")),
                 dict(force_harmonic=True, force_phase=float("inf")),
                 dict(metric=np.ones((4, 16, 16)), dx_min=0.0),
-                dict(metric=np.ones((4, 16, 16)), dx_min=0.1, inv_dx_x=np.ones(16))):
+                dict(metric=np.ones((4, 16, 16)), dx_min=0.1, inv_dx_x=np.ones(16)),
+                dict(mass_source=np.zeros((16, 16)), pl_n=0.5, nu_min=1e-3, nu_max=1.0)):
         p, keep = _params(L, **bad)
         assert L.mdf_workspace_size(p) == 0, bad
+    # a mass source adds one plane of nx*ny values
+    p, keep = _params(L, mass_source=np.zeros((16, 16)))
+    assert L.mdf_workspace_size(p) == n + 16 * 16 * 8
 
 
 def test_init_rejects_bad_input_without_device_work(L):
@@ -151,6 +155,9 @@ def test_batch_validation_without_device_work(L):
     assert L.mdf_batch_workspace_size((L.mdf_params * 2)(good[0], params_of(osc, keep)), 2) == 0
     warped = P.warped_taylor_green(32)
     assert L.mdf_batch_workspace_size((L.mdf_params * 2)(good[0], params_of(warped, keep)), 2) == 0
+    src = P.divergent_flow(32)
+    src.force_x = src.force_y = None
+    assert L.mdf_batch_workspace_size((L.mdf_params * 2)(good[0], params_of(src, keep)), 2) == 0
     out = C.c_void_p()
     arrp = (C.c_void_p * 3)()
     s = L.lib().mdf_batch_init(arr, 3, arrp, arrp, arrp, None, 0, None, C.byref(out))
