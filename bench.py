@@ -37,6 +37,10 @@ BYTES_PER_NODE = 160.0         # 10 FP64 planes read + 10 written per node and s
 # writes f_bar^+ (160 B), pass B reads f_bar^+ and the 4 metric values and writes f(t+h)
 # (192 B), pass C reads f_hat, f(t+h) and the metric and writes f_hat(t+dt) (272 B).
 MAPPED_THREE_PASS_BYTES = 624.0
+# The three-pass step with a mass source and a force field on a uniform grid, per node: pass A
+# reads f_hat and R and writes f_bar^+ (168 B), pass B reads f_bar^+, R and (F_x, F_y) and writes
+# f(t+h) (184 B), pass C reads f_hat, f(t+h), R and the force and writes f_hat(t+dt) (264 B).
+SOURCE_THREE_PASS_BYTES = 616.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2306_08216_amd", "csrc")
 TUNING = os.path.join(ROOT, "paper_2306_08216_amd", "tuning_mi355x.json")
@@ -397,8 +401,9 @@ def main():
 
 
 def secondary_lines(args):
-    """Context lines: the 1024^2 cavity (cache-resident pair), the batch, and the
-    trapezoidal cavity on a general mapping (three-pass step)."""
+    """Context lines: the 1024^2 cavity (cache-resident pair), the batch, the
+    trapezoidal cavity on a general mapping and the divergent flow with a mass
+    source (both on the three-pass step)."""
     from paper_2306_08216_amd import problems as P
 
     class A:
@@ -425,7 +430,15 @@ def secondary_lines(args):
                         "the metric read twice)",
             "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "achieved_GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4), "steps": a.steps, "diagnostics": r["diagnostics"]}
-    return {"cavity1024": cav, "batch256": bat, "trapezoid2048": trap}
+    prob = P.divergent_flow(2048)
+    r = run_solver(prob, a, "divergent2048", 200)
+    gbs = SOURCE_THREE_PASS_BYTES * prob.nodes / (r["ms_per_step"] / 1e3) / 1e9
+    src = {"workload": "steady divergent flow with a mass source R (eq. 2.1.1) and its balancing force field, "
+                       "periodic 2048x2048, three-pass step (616 B per node: f_hat read twice, two intermediates "
+                       "written and read, R read three times, the force field twice)",
+           "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "achieved_GBs": round(gbs, 1),
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "steps": a.steps, "diagnostics": r["diagnostics"]}
+    return {"cavity1024": cav, "batch256": bat, "trapezoid2048": trap, "divergent2048": src}
 
 
 def bench_batch(args):

@@ -61,6 +61,9 @@ struct orc_state {
     double kap[4];            /* their kappa: dt/2, h/2, -h/2, 0 */
     /* alpha = 0 distributions (rho0), when tracked: f_hat, f_hat^+, f_bar^+, f_bar, f, new */
     double *r0hat, *r0hatp, *r0barp, *r0bar, *r0mid, *r0new;
+    /* momentum flux (u u + P, u v, v u, v v + P) at the last two steps, and at this one */
+    double *q1, *q2, *qn;
+    int nq;                   /* how many of q1, q2 hold values */
     int64_t steps;
 };
 
@@ -666,6 +669,42 @@ int32_t orc_rho0(const orc_state* st, double* out)
 }
 
 /* ------------------------------------------------------------------ */
+/* the sources G and G_bar (eqs. 2.2.7 and 2.2.10)                     */
+/* ------------------------------------------------------------------ */
+
+/* Momentum flux at every node at the start of the step: for alpha = 1 the
+ * vector u_bar_1 u + P E_1 = (u u + P, u v), for alpha = 2 (v u, v v + P). */
+static void flux_now(orc_state* st)
+{
+    for (size_t i = 0; i < st->n; ++i) {
+        double phi[NPL], u, v, P;
+        gather(st, st->fhat, i, phi);
+        node_state(st, phi, FORM_HAT, source_at(st, i), &u, &v, &P);
+        st->qn[4 * i + 0] = u * u + P;
+        st->qn[4 * i + 1] = u * v;
+        st->qn[4 * i + 2] = v * u;
+        st->qn[4 * i + 3] = v * v + P;
+    }
+}
+
+/* Source of distribution j of equation alpha at node i from the flux history:
+ *   g  = w_j c_j . d_t(u_alpha u + P E_alpha) / c_s^2        (eq. 2.2.7)
+ *   dg = w_j c_j . d_tt(u_alpha u + P E_alpha) / c_s^2       (its d_t)
+ * with the backward differences (Q_n - Q_{n-1})/dt and
+ * (Q_n - 2 Q_{n-1} + Q_{n-2})/dt^2, zero while the steps before are missing. */
+static void flux_source_at(const orc_state* st, size_t i, int a, int j, double* g, double* dg)
+{
+    double d1[2] = {0.0, 0.0}, d2[2] = {0.0, 0.0};
+    for (int b = 0; b < 2; ++b) {
+        const double qn = st->qn[4 * i + 2 * a + b];
+        if (st->nq >= 1) d1[b] = (qn - st->q1[4 * i + 2 * a + b]) / st->dt;
+        if (st->nq >= 2) d2[b] = (qn - 2.0 * st->q1[4 * i + 2 * a + b] + st->q2[4 * i + 2 * a + b]) / (st->dt * st->dt);
+    }
+    *g = WJ[j] * st->c * (CX[j] * d1[0] + CY[j] * d1[1]) / st->cs2;
+    *dg = WJ[j] * st->c * (CX[j] * d2[0] + CY[j] * d2[1]) / st->cs2;
+}
+
+/* ------------------------------------------------------------------ */
 /* one time step                                                       */
 /* ------------------------------------------------------------------ */
 
@@ -680,6 +719,9 @@ static void one_step(orc_state* st)
     const int harmonic = st->p.force_harmonic != 0;
     const double m = harmonic ? cos(st->p.force_omega * tn + st->p.force_phase) : 1.0;
     const double dm = harmonic ? -st->p.force_omega * sin(st->p.force_omega * tn + st->p.force_phase) : 0.0;
+    /* G_bar = (I + h/2 S~)^-1 G with S~ = s I (eq. 2.2.10) */
+    const double gbar = st->qn ? 1.0 / (1.0 + 0.5 * st->h * st->cs2 / st->p.nu) : 0.0;
+    if (st->qn) flux_now(st);
 
     /* Step (1): f_hat^+ and f_bar^+ at every node. */
 #pragma omp parallel for schedule(static)
@@ -705,6 +747,12 @@ static void one_step(orc_state* st)
                     const double* pl = st->fbar_plus + (size_t)(a * NQ + j) * n;
                     st->fbar[(size_t)(a * NQ + j) * n + i] =
                         pl[i] - st->h * cdotgrad(st, pl, x, y, j) + st->h * WJ[j] * Fa[a][i] * m;
+                    if (st->qn) {
+                        /* + h [G_bar + (h/2) d_t G_bar]   (eq. 2.2.11) */
+                        double g, dg;
+                        flux_source_at(st, i, a, j, &g, &dg);
+                        st->fbar[(size_t)(a * NQ + j) * n + i] += st->h * gbar * (g + 0.5 * st->h * dg);
+                    }
                 }
         }
 
@@ -736,11 +784,24 @@ static void one_step(orc_state* st)
                                     - st->dt * cdotgrad(st, st->fmid + k, x, y, j)
                                     + st->dt * WJ[j] * Fa[a][i] * m
                                     + 0.5 * st->dt * st->dt * WJ[j] * Fa[a][i] * dm;
+                    if (st->qn) {
+                        /* + dt G + (dt^2/2) d_t G   (eq. 2.2.1) */
+                        double g, dg;
+                        flux_source_at(st, i, a, j, &g, &dg);
+                        st->fnew[k + i] += st->dt * g + 0.5 * st->dt * st->dt * dg;
+                    }
                 }
         }
     wall_update(st, st->fnew, FORM_HAT);
 
     if (st->r0hat) rho0_step(st);
+    if (st->qn) {
+        double* t2 = st->q2;
+        st->q2 = st->q1;
+        st->q1 = st->qn;
+        st->qn = t2;
+        if (st->nq < 2) st->nq += 1;
+    }
 
     double* t = st->fhat;
     st->fhat = st->fnew;
@@ -788,6 +849,7 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     if (p->track_rho0 != 0 &&
         (p->track_rho0 != 1 || p->pl_n != 1.0 || p->bc_x != ORC_PERIODIC || p->bc_y != ORC_PERIODIC))
         return NULL;
+    if (p->flux_source != 0 && (p->flux_source != 1 || p->pl_n != 1.0)) return NULL;
 
     orc_state* st = (orc_state*)calloc(1, sizeof(orc_state));
     st->p = *p;
@@ -857,6 +919,13 @@ orc_state* orc_create(const orc_params* p, const double* u0, const double* v0, c
     /* walls of the intermediate fields start equal to the state */
     memcpy(st->fnew, st->fhat, bytes);
 
+    if (p->flux_source) {
+        st->q1 = (double*)calloc(4 * st->n, sizeof(double));
+        st->q2 = (double*)calloc(4 * st->n, sizeof(double));
+        st->qn = (double*)calloc(4 * st->n, sizeof(double));
+        st->nq = 0;
+    }
+
     /* rho0 = 1 at rest in the velocity field: f_hat_0 = f^eq_0(1, u0) */
     if (p->track_rho0) {
         size_t b0 = sizeof(double) * NQ * st->n;
@@ -896,6 +965,9 @@ void orc_destroy(orc_state* st)
     free(st->r0bar);
     free(st->r0mid);
     free(st->r0new);
+    free(st->q1);
+    free(st->q2);
+    free(st->qn);
     free(st);
 }
 

@@ -57,6 +57,12 @@ typedef struct {
      * the velocity equations do not need; a check of that remark.  Periodic axes and a
      * Newtonian fluid only.  0: not carried. */
     int32_t track_rho0;
+    /* 1: add the sources G and G_bar of eqs. 2.2.7 and 2.2.10 with their time-derivative
+     * terms (eqs. 2.2.1 and 2.2.11), which Remark 2 drops, taking d_t of the momentum flux
+     * u_alpha u + P E_alpha by backward differences over the previous steps (zero until
+     * those steps exist).  Newtonian fluid only.  0: dropped, as in every computation of
+     * the paper. */
+    int32_t flux_source;
 } orc_params;
 
 typedef struct orc_state orc_state;

@@ -36,6 +36,7 @@ class OrcParams(C.Structure):
         ("metric", _dp),
         ("mass_source", _dp),
         ("track_rho0", C.c_int32),
+        ("flux_source", C.c_int32),
     ]
 
 
@@ -137,7 +138,7 @@ def _params(prob):
                   prob.cfl, prob.c, prob.eta, prob.s_ratio, prob.bc_x, prob.bc_y, prob.lid_u,
                   prob.fx, prob.fy, _ptr(gx), _ptr(gy), prob.dx_min, _ptr(ffx), _ptr(ffy),
                   prob.force_omega, prob.force_phase, int(prob.force_harmonic), _ptr(met),
-                  _ptr(rs), int(getattr(prob, "track_rho0", 0)))
+                  _ptr(rs), int(getattr(prob, "track_rho0", 0)), int(getattr(prob, "flux_source", 0)))
     return p, keep
 
 

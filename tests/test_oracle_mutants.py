@@ -112,6 +112,10 @@ CASES = [
     ("alpha = 0 equation without its source in Step (4)",
      "+ st->dt * WJ[q] * source_at(st, i);", ";",
      "test_oracle_source", "test_rho0_equation_stays_uniform"),
+    ("source G of eq. 2.2.7 without its 1/c_s^2",
+     "*g = WJ[j] * st->c * (CX[j] * d1[0] + CY[j] * d1[1]) / st->cs2;",
+     "*g = WJ[j] * st->c * (CX[j] * d1[0] + CY[j] * d1[1]);",
+     "test_oracle_source", "test_flux_source_moments_on_a_uniform_flow"),
     ("wall rule taking the neighbour pressures without the mass source",
      "node_state(st, ph1, form, source_at(st, i1), &u1, &v1, &P1);",
      "node_state(st, ph1, form, 0.0, &u1, &v1, &P1);",

@@ -135,3 +135,64 @@ def test_source_parameters_are_validated(orc):
     o = orc.Oracle(prob)
     with pytest.raises(ValueError):
         o.rho0()
+
+
+# ---- the sources G and G_bar of eqs. 2.2.7 and 2.2.10 (dropped by Remark 2) ----
+
+def test_flux_source_moments_on_a_uniform_flow(orc):
+    """G of eq. 2.2.7 with its moments of eq. 2.3.5: on a uniform flow driven by
+    an oscillating uniform force no gradient acts, so after the second step
+    (the first with a flux history; the first step carries no G) the state
+    with G differs from the plain one by exactly dt G(t_1) = w_j c_j . (Q(t_1) -
+    Q(t_0)) / c_s^2, Q_alpha = u_alpha u + P E_alpha: zero in the zeroth moment,
+    the flux increment in the first."""
+    def run(fs, steps):
+        prob = P.taylor_green(16, u0=0.0)
+        prob.u0 = np.full((16, 16), 0.02)
+        prob.v0 = np.full((16, 16), -0.01)
+        prob.p0 = np.full((16, 16), 1e-3)
+        prob.fx, prob.fy = 2e-3, 1e-3
+        prob.force_harmonic, prob.force_omega = True, 0.7
+        prob.flux_source = fs
+        o = orc.Oracle(prob)
+        o.step(steps)
+        return o
+    assert np.array_equal(run(0, 1).f(), run(1, 1).f())
+    q = []
+    for steps in (0, 1):
+        u, v, p = run(0, steps).moments()
+        q.append(np.array([u[0, 0] ** 2 + p[0, 0], u[0, 0] * v[0, 0], v[0, 0] * u[0, 0], v[0, 0] ** 2 + p[0, 0]]))
+    dq = q[1] - q[0]
+    diff = run(1, 2).f() - run(0, 2).f()
+    c = 1.0
+    cx, cy = c * np.array([0, 1, 0, -1, 0.0]), c * np.array([0, 0, 1, 0, -1.0])
+    for a in range(2):
+        d = diff[5 * a:5 * a + 5, 3, 5]
+        assert abs(d.sum()) < 1e-18
+        assert abs((cx * d).sum() - dq[2 * a]) < 1e-15
+        assert abs((cy * d).sum() - dq[2 * a + 1]) < 1e-15
+        assert np.allclose(d, 0.2 * (cx * dq[2 * a] + cy * dq[2 * a + 1]) / 0.4, rtol=0, atol=1e-17)
+
+
+def test_flux_source_destabilises_the_scheme_at_rest(orc):
+    """Why Remark 2's dropping of G is kept here: at rest G reduces to its
+    pressure part w_j c_j . d_t(P E_alpha)/c_s^2, whose first moments add the
+    last step's pressure increment to the trace of the first moments.  That trace
+    is what the pressure of eq. 2.3.23 reads, and the collision keeps it, so the
+    pressure integrates its own increments.  Seeded noise of 1e-8 on a fluid at
+    rest (32^2, nu = 0.01, CFL 0.1) decays by 0.1x in 200 plain steps and grows
+    by over 1e6x with G."""
+    rng = np.random.default_rng(3)
+    noise = 1e-8 * rng.standard_normal((10, 32, 32))
+    growth = []
+    for fs in (0, 1):
+        prob = P.taylor_green(32, u0=0.0, nu=0.01, cfl=0.1)
+        prob.flux_source = fs
+        o = orc.Oracle(prob, threads=THREADS)
+        o.set_f(o.f() + noise)
+        f0 = o.f()
+        n0 = np.abs(f0 - f0.mean(axis=(1, 2), keepdims=True)).max()
+        o.step(200)
+        f1 = o.f()
+        growth.append(np.abs(f1 - f1.mean(axis=(1, 2), keepdims=True)).max() / n0)
+    assert growth[0] < 0.5 and growth[1] > 1e3, growth
