@@ -88,7 +88,7 @@ Layout layout_for(int nx, int ny, bool force_field, bool metric, bool source)
     L.off_fmid = o; o += fbytes;
     L.off_gx = o;   o += align256((size_t)nx * sizeof(double));
     L.off_gy = o;   o += align256((size_t)ny * sizeof(double));
-    L.off_dp = o;   o += align256(8 * 1024 * sizeof(double));
+    L.off_dp = o;   o += align256(8 * (size_t)mdf::kDiagMaxBlocks * sizeof(double));
     L.off_do = o;   o += align256(16 * sizeof(double));   // diagnostics result (8), closure guard state (4)
     L.off_seg = o;  o += align256(kSegCap * sizeof(int4));
     // force field: (F_x, F_y) per node in rows of pitch nodes
@@ -440,7 +440,7 @@ BatchLayout batch_layout(const mdf_params* ps, int count)
     B.off_f0 = t;     t += o;
     B.off_f1 = t;     t += o;
     B.off_backup = t; t += o;
-    B.off_dp = t;     t += align256(8 * 1024 * sizeof(double));   // diagnostics partials
+    B.off_dp = t;     t += align256(8 * (size_t)mdf::kDiagMaxBlocks * sizeof(double));   // diagnostics partials
     B.off_do = t;     t += align256(8 * sizeof(double));
     B.total = t;
     return B;

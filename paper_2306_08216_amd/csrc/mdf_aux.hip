@@ -41,63 +41,6 @@ __device__ __forceinline__ bool wall_neighbours(const StepConsts& K, int x, int 
     return true;
 }
 
-// component q at (x, y) where one coordinate may be one node beyond a wall
-// (quadratic ghost) or outside a periodic range (wrapped)
-__device__ __forceinline__ double fetch(const StepConsts& K, const double* f, int q, int x, int y)
-{
-    if (!K.bcx) x = x < 0 ? x + K.nx : (x >= K.nx ? x - K.nx : x);
-    if (!K.bcy) y = y < 0 ? y + K.ny : (y >= K.ny ? y - K.ny : y);
-    if (x == -1) return ghost(comp(K, f, 0, y, q), comp(K, f, 1, y, q), comp(K, f, 2, y, q));
-    if (x == K.nx)
-        return ghost(comp(K, f, K.nx - 1, y, q), comp(K, f, K.nx - 2, y, q),
-                     comp(K, f, K.nx - 3, y, q));
-    if (y == -1) return ghost(comp(K, f, x, 0, q), comp(K, f, x, 1, q), comp(K, f, x, 2, q));
-    if (y == K.ny)
-        return ghost(comp(K, f, x, K.ny - 1, q), comp(K, f, x, K.ny - 2, q),
-                     comp(K, f, x, K.ny - 3, q));
-    return comp(K, f, x, y, q);
-}
-
-// tau c_j . grad Pi_j at an interior node (lam = tau c / 2), component q = alpha*5 + j
-__device__ __forceinline__ double transport_at(const StepConsts& K, const double* f, int q, int x, int y, double lam)
-{
-    const int j = q % 5;
-    if (j == 0) return 0.0;
-    if (K.met) {
-        // general mapping: c_j . grad = U d/di + V d/dj with U = c_j . grad i and
-        // V = c_j . grad j at the node, each index difference upwinded by the
-        // sign of its own component
-        const size_t n = (size_t)K.nx * K.ny, i = (size_t)y * K.nx + x;
-        const double cx = j == 1 ? 1.0 : (j == 3 ? -1.0 : 0.0), cy = j == 2 ? 1.0 : (j == 4 ? -1.0 : 0.0);
-        const double U = cx * K.met[i] + cy * K.met[n + i], V = cx * K.met[2 * n + i] + cy * K.met[3 * n + i];
-        const double p0 = fetch(K, f, q, x, y);
-        double r = 0.0;
-        if (U > 0.0)
-            r += transport_pos(K, lam * U, fetch(K, f, q, x - 2, y), fetch(K, f, q, x - 1, y), p0,
-                               fetch(K, f, q, x + 1, y));
-        else if (U < 0.0)
-            r += transport_neg(K, -lam * U, fetch(K, f, q, x - 1, y), p0, fetch(K, f, q, x + 1, y),
-                               fetch(K, f, q, x + 2, y));
-        if (V > 0.0)
-            r += transport_pos(K, lam * V, fetch(K, f, q, x, y - 2), fetch(K, f, q, x, y - 1), p0,
-                               fetch(K, f, q, x, y + 1));
-        else if (V < 0.0)
-            r += transport_neg(K, -lam * V, fetch(K, f, q, x, y - 1), p0, fetch(K, f, q, x, y + 1),
-                               fetch(K, f, q, x, y + 2));
-        return r;
-    }
-    if (j == 1 || j == 3) {
-        const double lg = lam * gx_at(K, x);
-        const double pm1 = fetch(K, f, q, x - 1, y), p0 = fetch(K, f, q, x, y), p1 = fetch(K, f, q, x + 1, y);
-        if (j == 1) return transport_pos(K, lg, fetch(K, f, q, x - 2, y), pm1, p0, p1);
-        return transport_neg(K, lg, pm1, p0, p1, fetch(K, f, q, x + 2, y));
-    }
-    const double lg = lam * gy_at(K, y);
-    const double pm1 = fetch(K, f, q, x, y - 1), p0 = fetch(K, f, q, x, y), p1 = fetch(K, f, q, x, y + 1);
-    if (j == 2) return transport_pos(K, lg, fetch(K, f, q, x, y - 2), pm1, p0, p1);
-    return transport_neg(K, lg, pm1, p0, p1, fetch(K, f, q, x, y + 2));
-}
-
 __global__ void k_init(StepConsts K, const double* __restrict__ u0, const double* __restrict__ v0,
                        const double* __restrict__ p0, double* __restrict__ f)
 {
@@ -224,59 +167,75 @@ __device__ __forceinline__ void block_reduce8(double* vals, double* part)
     }
 }
 
+// Tiles of 64 x 16 nodes: the block loads every node of the tile and of a
+// one-node halo around it once, keeps (u, v) in LDS, and adds each tile
+// node's own terms as it loads it; then the central-difference divergence of
+// every non-wall tile node reads its neighbours from LDS.  A block walks its
+// tiles in a fixed order and writes 8 partials; the final kernel reduces them
+// in order.
+constexpr int DT_X = 64, DT_Y = 16, DH_X = DT_X + 2, DH_Y = DT_Y + 2;
+
 __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const double* __restrict__ f,
                                                               double* __restrict__ partials)
 {
-    const long long n = (long long)K.nx * K.ny;
+    __shared__ double tu[DH_Y][DH_X], tv[DH_Y][DH_X];
+    const int tiles_x = (K.nx + DT_X - 1) / DT_X, tiles = tiles_x * ((K.ny + DT_Y - 1) / DT_Y);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (long long s = (long long)blockIdx.x * DIAG_BLOCK + threadIdx.x; s < n; s += (long long)gridDim.x * DIAG_BLOCK) {
-        const int x = (int)(s % K.nx), y = (int)(s / K.nx);
-        double fh[10], d[14], u, v, P;
-        load10(K, f, x, y, fh);
-        node_moments(fh, K.c, u, v, P);
-        derived_node(K, fh, x, y, d);
-        double dA = 1.0 / (gx_at(K, x) * gy_at(K, y));
-        const size_t nn = (size_t)K.nx * K.ny, ii = (size_t)y * K.nx + x;
-        if (K.met) dA = 1.0 / fabs(K.met[ii] * K.met[3 * nn + ii] - K.met[nn + ii] * K.met[2 * nn + ii]);
-        acc[0] += u;
-        acc[1] += v;
-        acc[2] += 0.5 * (u * u + v * v) * dA;
-        acc[3] += 0.5 * d[12] * d[12] * dA;
-        acc[4] = fmax(acc[4], sqrt(u * u + v * v));
-        if (!is_wall(K, x, y)) {
-            const int xp = x + 1 == K.nx ? 0 : x + 1, xm = x == 0 ? K.nx - 1 : x - 1;
-            const int yp = y + 1 == K.ny ? 0 : y + 1, ym = y == 0 ? K.ny - 1 : y - 1;
-            double a[10], b[10], t0, t1, t2, ue, uw, vn, vs;
-            load10(K, f, xp, y, a);
-            node_moments(a, K.c, ue, t1, t2);
-            load10(K, f, xm, y, b);
-            node_moments(b, K.c, uw, t1, t2);
-            load10(K, f, x, yp, a);
-            node_moments(a, K.c, t0, vn, t2);
-            load10(K, f, x, ym, b);
-            node_moments(b, K.c, t0, vs, t2);
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int x0 = (t % tiles_x) * DT_X, y0 = (t / tiles_x) * DT_Y;
+        for (int c = threadIdx.x; c < DH_X * DH_Y; c += DIAG_BLOCK) {
+            const int cy = c / DH_X, cx = c - cy * DH_X;
+            int x = x0 - 1 + cx, y = y0 - 1 + cy;
+            // wrapped on a periodic axis; beyond a wall (or past the grid) the cell is
+            // never read: only wall nodes, which take no divergence, border it
+            if (!K.bcx) x = x < 0 ? x + K.nx : (x >= K.nx ? x - K.nx : x);
+            if (!K.bcy) y = y < 0 ? y + K.ny : (y >= K.ny ? y - K.ny : y);
+            double u = 0.0, v = 0.0;
+            if (x >= 0 && x < K.nx && y >= 0 && y < K.ny) {
+                double fh[10], P;
+                load10(K, f, x, y, fh);
+                node_moments(fh, K.c, u, v, P);
+                const bool own = cx >= 1 && cx <= DT_X && cy >= 1 && cy <= DT_Y && x0 - 1 + cx < K.nx &&
+                                 y0 - 1 + cy < K.ny;
+                if (own) {
+                    double d[14];
+                    derived_node(K, fh, x, y, d);
+                    double dA = 1.0 / (gx_at(K, x) * gy_at(K, y));
+                    const size_t nn = (size_t)K.nx * K.ny, ii = (size_t)y * K.nx + x;
+                    if (K.met) dA = 1.0 / fabs(K.met[ii] * K.met[3 * nn + ii] - K.met[nn + ii] * K.met[2 * nn + ii]);
+                    acc[0] += u;
+                    acc[1] += v;
+                    acc[2] += 0.5 * (u * u + v * v) * dA;
+                    acc[3] += 0.5 * d[12] * d[12] * dA;
+                    acc[4] = fmax(acc[4], sqrt(u * u + v * v));
+                    int bad = 0;
+#pragma unroll
+                    for (int k = 0; k < 10; ++k) bad += isfinite(fh[k]) ? 0 : 1;
+                    acc[6] += (double)bad;
+                    acc[7] += dA;
+                }
+            }
+            tu[cy][cx] = u;
+            tv[cy][cx] = v;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < DT_X * DT_Y; c += DIAG_BLOCK) {
+            const int ly = c / DT_X, lx = c - ly * DT_X;
+            const int x = x0 + lx, y = y0 + ly;
+            if (x >= K.nx || y >= K.ny || is_wall(K, x, y)) continue;
+            const int cx = lx + 1, cy = ly + 1;
+            const double ue = tu[cy][cx + 1], uw = tu[cy][cx - 1], un = tu[cy + 1][cx], us = tu[cy - 1][cx];
+            const double ve = tv[cy][cx + 1], vw = tv[cy][cx - 1], vn = tv[cy + 1][cx], vs = tv[cy - 1][cx];
             double div = (ue - uw) * gx_at(K, x) * 0.5 + (vn - vs) * gy_at(K, y) * 0.5;
             if (K.met) {
                 // chain rule: du/dx + dv/dy from both index differences of u and v
-                double un, us, ve, vw;
-                load10(K, f, x, yp, a);
-                node_moments(a, K.c, un, t1, t2);
-                load10(K, f, x, ym, b);
-                node_moments(b, K.c, us, t1, t2);
-                load10(K, f, xp, y, a);
-                node_moments(a, K.c, t0, ve, t2);
-                load10(K, f, xm, y, b);
-                node_moments(b, K.c, t0, vw, t2);
+                const size_t nn = (size_t)K.nx * K.ny, ii = (size_t)y * K.nx + x;
                 div = K.met[ii] * (ue - uw) * 0.5 + K.met[2 * nn + ii] * (un - us) * 0.5 +
                       K.met[nn + ii] * (ve - vw) * 0.5 + K.met[3 * nn + ii] * (vn - vs) * 0.5;
             }
             acc[5] = fmax(acc[5], fabs(div));
         }
-        int bad = 0;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) bad += isfinite(fh[k]) ? 0 : 1;
-        acc[6] += (double)bad;
-        acc[7] += dA;
+        __syncthreads();
     }
     block_reduce8(acc, partials + 8 * blockIdx.x);
 }
@@ -373,96 +332,30 @@ __global__ __launch_bounds__(256) void k_pass_a(StepConsts K, const double* __re
     store10(K, fbp, x, y, out);
 }
 
-// f(t+h) at an interior node: half step (eq. 2.3.25 in Taylor form) then Step (3)
+// Wall nodes of a field the tiled pass has just written at every interior
+// node (f(t+h) after pass B, f_hat(t+dt) after pass C): the wall rule from the
+// two inward neighbours, which are interior nodes, as the method applies it
+// after each sub-step.  r is the pressure offset per unit source of the
+// field's stored form.  One thread per perimeter wall node.
 template <bool SRC>
-__device__ __forceinline__ void mid_at(const StepConsts& K, const double* fbp, int x, int y, double* f)
-{
-    double fb[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k)
-        fb[k] = comp(K, fbp, x, y, k) - transport_at(K, fbp, k, x, y, K.lam_h) + hwf_at(K, x, y, k / 5);
-    collide3<SRC>(K, fb, f, src_dp<SRC>(K, K.r_bar, x, y));
-}
-
-// Wall nodes (one thread per perimeter node; the interior is k_pass_tiled):
-// a wall node extrapolates from its two inward neighbours, and one loop over
-// them keeps a single inlined copy of the node update (three copies spilled
-// to scratch).
-template <bool SRC>
-__global__ __launch_bounds__(256) void k_pass_b(StepConsts K, const double* __restrict__ fbp,
-                                                double* __restrict__ fmid)
+__global__ __launch_bounds__(256) void k_perimeter_wall(StepConsts K, double* __restrict__ f, double r)
 {
     int x, y;
     if (!perimeter_node(K, (int)(blockIdx.x * blockDim.x + threadIdx.x), x, y)) return;
     int x1, y1, x2, y2;
-    double uw = 0.0, p1[10], p2[10];
-    const bool wall = wall_neighbours(K, x, y, x1, y1, x2, y2, uw);
-    const int cnt = wall ? 2 : 1;
-#pragma nounroll
-    for (int t = 0; t < cnt; ++t) {
-        double v[10];
-        mid_at<SRC>(K, fbp, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            if (t == 0) p1[k] = v[k];
-            else p2[k] = v[k];
-        }
-    }
-    if (wall) {
-        double out[10];
-        wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, K.r_f, x1, y1), src_dp<SRC>(K, K.r_f, x2, y2));
-        store10(K, fmid, x, y, out);
-    } else {
-        store10(K, fmid, x, y, p1);
-    }
-}
-
-// f_hat(t+dt) at an interior node: Step (4), eq. 2.3.24
-template <bool SRC>
-__device__ __forceinline__ void full_at(const StepConsts& K, const double* fh, const double* fmid, int x, int y,
-                                        double* out)
-{
-    double a[10], fhp[10];
-    load10(K, fh, x, y, a);
-    collide1_hat<SRC>(K, a, fhp, src_dp<SRC>(K, K.r_hat, x, y));
-#pragma unroll
-    for (int k = 0; k < 10; ++k) out[k] = fhp[k] - transport_at(K, fmid, k, x, y, K.lam_dt) + dwf_at(K, x, y, k / 5);
-}
-
-template <bool SRC>
-__global__ __launch_bounds__(256) void k_pass_c(StepConsts K, const double* __restrict__ fh,
-                                                const double* __restrict__ fmid, double* __restrict__ fnew)
-{
-    int x, y;
-    if (!perimeter_node(K, (int)(blockIdx.x * blockDim.x + threadIdx.x), x, y)) return;
-    int x1, y1, x2, y2;
-    double uw = 0.0, p1[10], p2[10];
-    const bool wall = wall_neighbours(K, x, y, x1, y1, x2, y2, uw);
-    const int cnt = wall ? 2 : 1;
-#pragma nounroll
-    for (int t = 0; t < cnt; ++t) {
-        double v[10];
-        full_at<SRC>(K, fh, fmid, wall ? (t == 0 ? x1 : x2) : x, wall ? (t == 0 ? y1 : y2) : y, v);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            if (t == 0) p1[k] = v[k];
-            else p2[k] = v[k];
-        }
-    }
-    if (wall) {
-        double out[10];
-        wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, K.r_hat, x1, y1), src_dp<SRC>(K, K.r_hat, x2, y2));
-        store10(K, fnew, x, y, out);
-    } else {
-        store10(K, fnew, x, y, p1);
-    }
+    double uw = 0.0, p1[10], p2[10], out[10];
+    if (!wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) return;
+    load10(K, f, x1, y1, p1);
+    load10(K, f, x2, y2, p2);
+    wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, r, x1, y1), src_dp<SRC>(K, r, x2, y2));
+    store10(K, f, x, y, out);
 }
 
 // ---- tiled sub-steps of the three-pass step (interior nodes) ----
 // A 64 x 4 tile of nodes stages its input field with a halo of 2 in LDS, so
 // each stencil value is loaded from memory once per tile instead of once per
-// use; the stencil then reads LDS.  Wall nodes keep the per-node code above
-// (k_pass_b / k_pass_c over the perimeter only).
+// use; the stencil then reads LDS.  Wall nodes are set afterwards from the
+// written interior (k_perimeter_wall).
 constexpr int TB_X = 64, TB_Y = 4, TB_HALO = 2;
 constexpr int TS_X = TB_X + 2 * TB_HALO, TS_Y = TB_Y + 2 * TB_HALO;
 
@@ -604,9 +497,8 @@ hipError_t launch_derived(const StepConsts& K, const double* f, double* out, uin
 
 int diag_blocks(const StepConsts& K)
 {
-    const long long n = (long long)K.nx * K.ny;
-    long long b = (n + DIAG_BLOCK - 1) / DIAG_BLOCK;
-    return (int)(b < 1024 ? b : 1024);
+    const long long tiles = (long long)((K.nx + DT_X - 1) / DT_X) * ((K.ny + DT_Y - 1) / DT_Y);
+    return (int)(tiles < kDiagMaxBlocks ? tiles : kDiagMaxBlocks);
 }
 
 hipError_t launch_diagnostics(const StepConsts& K, const double* f, double* partials, double* out8, hipStream_t s)
@@ -668,9 +560,9 @@ void three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid
     const int nper = perimeter_count(K);
     hipLaunchKernelGGL(k_pass_a<SRC>, grid2d(K, b), b, 0, s, K, fh, fbp);
     hipLaunchKernelGGL((k_pass_tiled<false, SRC>), grid2d(K, bt), bt, 0, s, K, fbp, nullptr, fmid);
-    if (nper > 0) hipLaunchKernelGGL(k_pass_b<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fbp, fmid);
+    if (nper > 0) hipLaunchKernelGGL(k_perimeter_wall<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fmid, K.r_f);
     hipLaunchKernelGGL((k_pass_tiled<true, SRC>), grid2d(K, bt), bt, 0, s, K, fmid, fh, fnew);
-    if (nper > 0) hipLaunchKernelGGL(k_pass_c<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fh, fmid, fnew);
+    if (nper > 0) hipLaunchKernelGGL(k_perimeter_wall<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fnew, K.r_hat);
 }
 }  // namespace
 

@@ -13,6 +13,8 @@ hipError_t launch_init(const StepConsts& K, const double* u0, const double* v0, 
 hipError_t launch_wall_fix(const StepConsts& K, double* f, hipStream_t s);
 hipError_t launch_moments(const StepConsts& K, const double* f, double* u, double* v, double* p, hipStream_t s);
 hipError_t launch_derived(const StepConsts& K, const double* f, double* out, uint32_t mask, hipStream_t s);
+// diagnostics partials: 8 doubles per block of the reduction, at most this many blocks
+constexpr int kDiagMaxBlocks = 4096;
 int diag_blocks(const StepConsts& K);
 hipError_t launch_diagnostics(const StepConsts& K, const double* f, double* partials, double* out8, hipStream_t s);
 hipError_t launch_pack(const StepConsts& K, const double* f, double* dense, hipStream_t s);
