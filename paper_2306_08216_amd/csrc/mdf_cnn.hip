@@ -49,6 +49,12 @@ struct ConvArgs {
     int B, H, W;                // W a multiple of 32
 };
 
+// CIN_PAD (the input channel stride, 8 or 32) is a template argument so that
+// every operand of the 9 taps is loaded into registers before the MFMA chain
+// consumes them, instead of each MFMA waiting for its own two loads (the
+// layers are latency-bound at the closure's grid sizes).  The MFMAs
+// accumulate in the same order as a tap-by-tap loop.
+template <int CIN_PAD>
 __global__ __launch_bounds__(64) void k_conv(ConvArgs A)
 {
     const int tiles_x = A.W / 32;
@@ -57,18 +63,25 @@ __global__ __launch_bounds__(64) void k_conv(ConvArgs A)
     const int row = tile / tiles_x;   // b * H + y
     const int y = row % A.H, b = row / A.H;
     const int lane = threadIdx.x, i = lane & 31, kh = lane >> 5;
-    f32x16 acc = {};
+    constexpr int NB = CIN_PAD / 8;
+    bf4 av[9][NB], bv[9][NB];
+#pragma unroll
     for (int t = 0; t < 9; ++t) {
         const int yy = (y + t / 3 - 1 + A.H) % A.H;
         const int xx = (x0 + i + t % 3 - 1 + A.W) % A.W;
-        const unsigned short* ap = A.in + ((size_t)(b * A.H + yy) * A.W + xx) * A.cin_pad + 4 * kh;
-        const unsigned short* wp = A.wp + ((size_t)t * 32 + i) * A.cin_pad + 4 * kh;
-        for (int cb = 0; cb < A.cin_pad; cb += 8) {
-            const bf4 av = *reinterpret_cast<const bf4*>(ap + cb);
-            const bf4 bv = *reinterpret_cast<const bf4*>(wp + cb);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+        const unsigned short* ap = A.in + ((size_t)(b * A.H + yy) * A.W + xx) * CIN_PAD + 4 * kh;
+        const unsigned short* wp = A.wp + ((size_t)t * 32 + i) * CIN_PAD + 4 * kh;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            av[t][c] = *reinterpret_cast<const bf4*>(ap + 8 * c);
+            bv[t][c] = *reinterpret_cast<const bf4*>(wp + 8 * c);
         }
     }
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[t][c], bv[t][c], acc, 0, 0, 0);
     // lane holds D[m][co] for co = lane % 32, m = 8 (r / 4) + 4 (lane / 32) + r % 4
     const int co = i;
 #pragma unroll
@@ -87,11 +100,20 @@ __global__ __launch_bounds__(64) void k_conv(ConvArgs A)
 //   wf[t][co][ci]  (cin_pad wide) for the forward convolution,
 //   wb[t][ci][co]  (cout_pad wide) = W[8 - t][ci][co] for the data gradient,
 // zero outside the layer's channels.
-__global__ void k_pack_weights(const float* __restrict__ params, int woff, int cin, int cout, int cin_pad,
-                               int cout_pad, unsigned short* __restrict__ wf, unsigned short* __restrict__ wb)
+struct PackArgs {
+    int woff[4], cin[4], cout[4], cin_pad[4], cout_pad[4];
+    unsigned short* wf[4];
+    unsigned short* wb[4];
+};
+
+__global__ void k_pack_weights(const float* __restrict__ params, PackArgs P)
 {
+    const int l = blockIdx.y;
+    const int cin = P.cin[l], cout = P.cout[l], cin_pad = P.cin_pad[l], cout_pad = P.cout_pad[l];
+    unsigned short* __restrict__ wf = P.wf[l];
+    unsigned short* __restrict__ wb = P.wb[l];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const float* W = params + woff;
+    const float* W = params + P.woff[l];
     if (e < 9 * 32 * cin_pad) {
         const int ci = e % cin_pad, co = (e / cin_pad) % 32, t = e / (32 * cin_pad);
         wf[e] = (co < cout && ci < cin) ? to_bf16(W[(t * cin + ci) * cout + co]) : 0;
@@ -440,13 +462,28 @@ int woff_of(int l)
 
 hipError_t pack_all(const CnnLayout& L, char* ws, const float* params, hipStream_t s)
 {
+    // the four layers in one launch (blockIdx.y = layer)
+    PackArgs A{};
     for (int l = 0; l < 4; ++l) {
-        const int n = 9 * 32 * 32;
-        hipLaunchKernelGGL(k_pack_weights, dim3((n + 255) / 256), dim3(256), 0, s, params, woff_of(l), kCh[l],
-                           kCh[l + 1], cin_pad_of(l), cout_pad_of(l), (unsigned short*)(ws + L.wf[l]),
-                           (unsigned short*)(ws + L.wb[l]));
+        A.woff[l] = woff_of(l);
+        A.cin[l] = kCh[l];
+        A.cout[l] = kCh[l + 1];
+        A.cin_pad[l] = cin_pad_of(l);
+        A.cout_pad[l] = cout_pad_of(l);
+        A.wf[l] = (unsigned short*)(ws + L.wf[l]);
+        A.wb[l] = (unsigned short*)(ws + L.wb[l]);
     }
+    const int n = 9 * 32 * 32;
+    hipLaunchKernelGGL(k_pack_weights, dim3((n + 255) / 256, 4), dim3(256), 0, s, params, A);
     return hipGetLastError();
+}
+
+void launch_conv(const ConvArgs& A, unsigned tiles, hipStream_t s)
+{
+    if (A.cin_pad == 8)
+        hipLaunchKernelGGL(k_conv<8>, dim3(tiles), dim3(64), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_conv<32>, dim3(tiles), dim3(64), 0, s, A);
 }
 
 ConvArgs conv_args(int B, int H, int W)
@@ -541,7 +578,7 @@ hipError_t forward_at(const CnnLayout& L, char* ws, const float* params, int B, 
         A.out_f32 = (float*)(ws + L.z[l + 1]);
         A.f32_stride = l < 3 ? 32 : 2;
         A.out_bf16 = l < 3 ? (unsigned short*)(ws + L.a[l + 1]) : nullptr;
-        hipLaunchKernelGGL(k_conv, dim3(tiles), dim3(64), 0, s, A);
+        launch_conv(A, tiles, s);
     }
     hipLaunchKernelGGL(k_unpack_output, dim3(nb), dim3(256), 0, s, (const float*)(ws + L.z[4]), B, H, W, out_scale,
                        duv);
@@ -634,7 +671,7 @@ hipError_t cnn_backward(char* ws, const float* params, int B, int H, int W, cons
         A.out_f32 = (float*)(ws + L.g32[l]);
         A.f32_stride = 32;
         A.out_bf16 = (unsigned short*)(ws + L.g16[l]);
-        hipLaunchKernelGGL(k_conv, dim3(tiles), dim3(64), 0, s, A);
+        launch_conv(A, tiles, s);
     }
     return hipGetLastError();
 }

@@ -293,3 +293,52 @@ def test_device_guard_matches_host_guard(gpu):
     a.close()
     b.close()
     del torch
+
+
+def test_captured_window_replays_match_eager_windows(gpu):
+    """A closure window captured as a HIP graph (K steps, the velocity, the
+    network, the guarded apply) and replayed gives, after every replay, exactly
+    the state and fall-back count of the same window launched eagerly on a
+    twin run; eager work on the replayed run's stream and synchronisations sit
+    between the replays.  The two runs take turns (they share the network's
+    fixed scratch array)."""
+    import torch
+    from paper_2306_08216_amd import _lib as L
+    from paper_2306_08216_amd.solver import Solver
+    prob = P.random_vortex(64, 11, 1e-4, kmax=24, urms=0.1)
+    net = gpu.ClosureNet(64, 64, 1, params=gpu.init_params(3, last_scale=1.0))
+    a = Solver(prob, stream=torch.cuda.Stream())
+    b = Solver(prob, stream=torch.cuda.Stream())
+    wa = gpu._Window(a, net, 4, 1.0, 2.0, graph=False)
+    wb = gpu._Window(b, net, 4, 1.0, 2.0, graph=True)
+    L.mdf_closure_begin(a.ctx)
+    L.mdf_closure_begin(b.ctx)
+    torch.cuda.synchronize()
+    for w in range(6):
+        wa()
+        torch.cuda.synchronize()
+        wb()
+        torch.cuda.synchronize()
+        fa, fb = a.save().cpu().numpy(), b.save().cpu().numpy()
+        say(f"[gpu closure] replay {w}: max|f_graph - f_eager| = {np.abs(fa - fb).max():.3e}")
+        assert np.array_equal(fa, fb), w
+        assert L.mdf_closure_stats(a.ctx)[:2] == L.mdf_closure_stats(b.ctx)[:2]
+        b.moments()                      # eager work on the replayed run's stream
+        torch.cuda.synchronize()
+    a.close()
+    b.close()
+
+
+def test_graph_rollout_matches_eager_rollout(gpu):
+    """The evaluation rollout replaying captured graphs (fine run, plain coarse
+    run and closure windows) ends on the same fields as the eager rollout."""
+    net = gpu.ClosureNet(64, 64, 1, params=gpu.init_params(5, last_scale=0.3))
+    kw = dict(n_coarse=64, ratio=2, nu=1e-4, K=4, steps=40, kmax=16, urms=0.05)
+    for model in (None, net):
+        r_e = gpu.rollout(21, model, graph=False, **kw)
+        r_g = gpu.rollout(21, model, graph=True, **kw)
+        say(f"[gpu closure] rollout {'closure' if model else 'plain'}: eager {r_e['rel_l2']:.6e} graph {r_g['rel_l2']:.6e}")
+        assert r_e["rel_l2"] == r_g["rel_l2"]
+        assert r_e["fallbacks"] == r_g["fallbacks"]
+        for x, y in zip(r_e["fine_ref"][:2], r_g["fine_ref"][:2]):
+            assert bool((x == y).all())
