@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--cpu-omp-steps", type=int, default=4, help="oracle steps per run on all cores")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary lines (1024^2 cavity, 256-instance batch)")
+    ap.add_argument("--no-closure", action="store_true",
+                    help="skip the learned-closure leg (training and evaluation, about 40 s)")
     ap.add_argument("--tuning", default=TUNING,
                     help="tuning cache: a kernel choice stored for this workload and device is used as is; "
                          "otherwise the autotuner runs and its choice is stored")
@@ -397,6 +399,8 @@ def main():
     }
     if args.workload == "powerlaw" and not args.no_secondary:
         out["secondary"] = secondary_lines(args)
+    if args.workload == "powerlaw" and not args.no_closure:
+        out["closure"] = bench_closure()
     print(json.dumps(out), flush=True)
 
 
@@ -439,6 +443,38 @@ def secondary_lines(args):
            "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "achieved_GBs": round(gbs, 1),
            "frac": round(gbs / HBM_PEAK_GBS, 4), "steps": a.steps, "diagnostics": r["diagnostics"]}
     return {"cavity1024": cav, "batch256": bat, "trapezoid2048": trap, "divergent2048": src}
+
+
+def bench_closure():
+    """The learned closure's half of the metric, measured here: the network is
+    trained on the GPU by the library's kernels on pairs the method generates
+    (64 seeds x 100 windows, 128^2 coarse against 512^2 fine, nu 5e-4, modes
+    |k| <= 24, u_rms 0.1), its gain is chosen on 8 validation seeds, and 8
+    held-out seeds are rolled out over 2000 coarse steps.  Reported: the
+    relative L2 velocity error of the plain coarse run and of the corrected one
+    against the fine run, and the wall time of the corrected run against the
+    fine run's (the fine run is the reference, so at <= 1 % error the closure's
+    speedup is the ratio of the two times)."""
+    from paper_2306_08216_amd import closure as CL
+    log("closure: generating pairs, training (8000 iterations), validating and evaluating")
+    t0 = time.time()
+    res = CL.experiment(list(range(64)), [1000 + i for i in range(8)], n_coarse=128, ratio=4, nu=5e-4, K=4,
+                        windows=100, horizon=2000, kmax=24, urms=0.1, batch=16, iters=8000,
+                        val_seeds=[2000 + i for i in range(8)], gains=(0.25, 0.5, 0.75, 1.0))
+    rows = res["test"]
+    plain = [r["plain_rel_l2"] for r in rows]
+    corr = [r["closure_rel_l2"] for r in rows]
+    t_fine = statistics.mean(r["t_fine_s"] for r in rows)
+    t_corr = statistics.mean(r["t_closure_s"] for r in rows)
+    return {"workload": "128^2 coarse + learned closure against 512^2 fine, periodic [0, 2pi]^2, k^-3 spectrum of "
+                        "modes 1 <= |k| <= 24, u_rms 0.1, nu 5e-4, 2000 coarse steps, K = 4",
+            "test_seeds": len(rows), "gain": res["gain"],
+            "rel_l2_plain_mean": round(statistics.mean(plain), 5), "rel_l2_plain_min": round(min(plain), 5),
+            "rel_l2_closure_mean": round(statistics.mean(corr), 5), "rel_l2_closure_max": round(max(corr), 5),
+            "seeds_at_or_below_1pct": sum(1 for e in corr if e <= 0.01),
+            "t_fine_s": round(t_fine, 5), "t_plain_coarse_s": round(statistics.mean(r["t_plain_s"] for r in rows), 5),
+            "t_closure_s": round(t_corr, 5), "speedup_vs_fine": round(t_fine / t_corr, 3),
+            "fallbacks": [r["fallbacks"] for r in rows], "wall_s": round(time.time() - t0, 1)}
 
 
 def bench_batch(args):
