@@ -352,11 +352,11 @@ __global__ __launch_bounds__(256) void k_perimeter_wall(StepConsts K, double* __
 }
 
 // ---- tiled sub-steps of the three-pass step (interior nodes) ----
-// A 64 x 4 tile of nodes stages its input field with a halo of 2 in LDS, so
+// A 64 x 8 tile of nodes stages the moving components of its input field with a halo of 2 in LDS, so
 // each stencil value is loaded from memory once per tile instead of once per
 // use; the stencil then reads LDS.  Wall nodes are set afterwards from the
 // written interior (k_perimeter_wall).
-constexpr int TB_X = 64, TB_Y = 4, TB_HALO = 2;
+constexpr int TB_X = 64, TB_Y = 8, TB_HALO = 2;
 constexpr int TS_X = TB_X + 2 * TB_HALO, TS_Y = TB_Y + 2 * TB_HALO;
 
 // All 10 components of node (x, y) of a stored field for the tile: wrapped on
@@ -418,13 +418,19 @@ __device__ __forceinline__ double transport_tile(const StepConsts& K, const doub
     return r;
 }
 
+// Only the eight moving components (j != 0) are streamed, so only they go
+// through the tile (a 64 x 8 tile and its halo: 52 KB of LDS, two workgroups
+// of eight waves per compute unit); slot s holds component q = s + 1 (s < 4)
+// or s + 2.
+__host__ __device__ constexpr int moving_slot(int q) { return q < 5 ? q - 1 : q - 2; }
+
 // FULL = false: pass B (half step of f_bar^+, then Step (3)) into f(t+h);
 // FULL = true: pass C (Step (4) on f(t+h) with f_hat^+ recomputed from f_hat).
 template <bool FULL, bool SRC>
 __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const double* __restrict__ src,
                                                            const double* __restrict__ fh, double* __restrict__ dst)
 {
-    __shared__ double tile[10][TS_Y][TS_X];
+    __shared__ double tile[8][TS_Y][TS_X];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int ox = (int)blockIdx.x * TB_X - TB_HALO, oy = (int)blockIdx.y * TB_Y - TB_HALO;
     for (int idx = ty * TB_X + tx; idx < TS_X * TS_Y; idx += TB_X * TB_Y) {
@@ -432,7 +438,8 @@ __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const d
         double phi[10];
         tile_node(K, src, ox + lx, oy + ly, phi);
 #pragma unroll
-        for (int q = 0; q < 10; ++q) tile[q][ly][lx] = phi[q];
+        for (int q = 0; q < 10; ++q)
+            if (q % 5 != 0) tile[moving_slot(q)][ly][lx] = phi[q];
     }
     __syncthreads();
     const int x = (int)blockIdx.x * TB_X + tx, y = (int)blockIdx.y * TB_Y + ty;
@@ -445,11 +452,12 @@ __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const d
         collide1_hat<SRC>(K, a, base, src_dp<SRC>(K, K.r_hat, x, y));
     } else {
 #pragma unroll
-        for (int q = 0; q < 10; ++q) base[q] = tile[q][cy][cx];
+        for (int q = 0; q < 10; ++q) base[q] = q % 5 == 0 ? comp(K, src, x, y, q) : tile[moving_slot(q)][cy][cx];
     }
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
-        const double tr = transport_tile(K, tile[q], cx, cy, q, x, y, FULL ? K.lam_dt : K.lam_h);
+        const double tr = q % 5 == 0 ? 0.0 : transport_tile(K, tile[moving_slot(q)], cx, cy, q, x, y,
+                                                             FULL ? K.lam_dt : K.lam_h);
         out[q] = base[q] - tr + (FULL ? dwf_at(K, x, y, q / 5) : hwf_at(K, x, y, q / 5));
     }
     if (FULL) {
