@@ -101,12 +101,15 @@ _lib = None
 
 
 def lib():
-    """Load libmdf.so (built by __graft_entry__.build()); fail loudly if absent."""
+    """Load libmdf.so (built by __graft_entry__.build()); fail loudly if absent.
+    The environment variable MDF_LIBRARY names another build of the same
+    sources to load instead (the checking build libmdf_poison.so)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
-        L = C.CDLL(LIB_PATH)
+        path = os.environ.get("MDF_LIBRARY", LIB_PATH)
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build the HIP library first (__graft_entry__.build())")
+        L = C.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
             fn.restype = res

@@ -2,6 +2,9 @@
 
 Every translation unit under csrc/ is compiled for gfx950 only, with packed
 FP32 instructions disabled, and linked into paper_2306_08216_amd/libmdf.so.
+The same sources are built a second time with MDF_POISON_LDS=1 into
+libmdf_poison.so, the checking build in which every LDS slot is set to NaN
+before the kernels publish in it (a test runs parity cases on it).
 """
 import concurrent.futures as cf
 import os
@@ -12,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmdf.so")
+LIB_POISON = os.path.join(HERE, "libmdf_poison.so")
 ROOT = os.path.dirname(HERE)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -28,9 +32,10 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+def _compile(src, verbose, poison=False):
+    out_dir = BUILD + "_poison" if poison else BUILD
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + (["-DMDF_POISON_LDS=1"] if poison else []) + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,17 +49,25 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
+def _link(objs, lib, verbose):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Both libraries: libmdf.so and the checking build libmdf_poison.so."""
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(BUILD + "_poison", exist_ok=True)
+    srcs = sources()
+    jobs = [(s, False) for s in srcs] + [(s, True) for s in srcs]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        objs = list(ex.map(lambda j: _compile(j[0], verbose, j[1]), jobs))
+    _link(objs[:len(srcs)], LIB, verbose)
+    _link(objs[len(srcs):], LIB_POISON, verbose)
     return LIB
 
 

@@ -183,6 +183,11 @@ __global__ __launch_bounds__(DIAG_BLOCK) void k_diag_partial(StepConsts K, const
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
         const int x0 = (t % tiles_x) * DT_X, y0 = (t / tiles_x) * DT_Y;
+        if constexpr (kPoisonLds) {
+            for (int c = threadIdx.x; c < DH_X * DH_Y; c += DIAG_BLOCK)
+                tu[c / DH_X][c % DH_X] = tv[c / DH_X][c % DH_X] = lds_poison_value();
+            __syncthreads();
+        }
         for (int c = threadIdx.x; c < DH_X * DH_Y; c += DIAG_BLOCK) {
             const int cy = c / DH_X, cx = c - cy * DH_X;
             int x = x0 - 1 + cx, y = y0 - 1 + cy;
@@ -433,6 +438,11 @@ __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const d
     __shared__ double tile[8][TS_Y][TS_X];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int ox = (int)blockIdx.x * TB_X - TB_HALO, oy = (int)blockIdx.y * TB_Y - TB_HALO;
+    if constexpr (kPoisonLds) {
+        for (int idx = ty * TB_X + tx; idx < 8 * TS_X * TS_Y; idx += TB_X * TB_Y)
+            (&tile[0][0][0])[idx] = lds_poison_value();
+        __syncthreads();
+    }
     for (int idx = ty * TB_X + tx; idx < TS_X * TS_Y; idx += TB_X * TB_Y) {
         const int ly = idx / TS_X, lx = idx - ly * TS_X;
         double phi[10];

@@ -21,6 +21,16 @@ namespace mdf {
 
 enum : int { PL_NEWTON = 0, PL_HALF = 1, PL_THREE_HALVES = 2 };
 
+// Checking build (libmdf_poison.so, compiled with MDF_POISON_LDS=1): every
+// LDS slot a kernel is about to publish in is first set to NaN, so a read of a
+// slot that no thread wrote for this row or tile carries a NaN into the
+// state, where the parity tests see it.  The released library has it off.
+#ifndef MDF_POISON_LDS
+#define MDF_POISON_LDS 0
+#endif
+constexpr bool kPoisonLds = MDF_POISON_LDS != 0;
+__device__ __forceinline__ double lds_poison_value() { return __builtin_nan(""); }
+
 // Constants of one run, computed on the host at mdf_init and passed by value.
 struct StepConsts {
     int nx, ny;

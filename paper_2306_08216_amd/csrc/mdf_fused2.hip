@@ -112,6 +112,10 @@ __device__ __forceinline__ void collide_moments(const StepConsts& K, double (*M)
 {
     const double s = ((phi[0] + phi[1]) + (phi[2] + phi[3])) + phi[4];
     const double q = K.c * (a == 0 ? phi[1] - phi[3] : phi[2] - phi[4]);
+    if constexpr (kPoisonLds) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) M[c][a][lane] = lds_poison_value();
+    }
     M[0][a][lane] = s;
     M[1][a][lane] = q;
     lds_barrier();
@@ -281,6 +285,10 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
         double bx[3];
         {
             double(*X)[TW2] = xch[0][a];
+            if constexpr (kPoisonLds) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) X[c][lane] = lds_poison_value();
+            }
             X[0][lane] = fbp[1];
             X[1][lane] = fbp[3];
             if (WX && wall_strip) {
@@ -346,6 +354,10 @@ __device__ __forceinline__ void fused2_march(const StepConsts& K, const double* 
         const bool outm = needB && (m >= ys0) && (m < ys1);
         if (outm) {
             double(*X)[TW2] = xch[1][a];
+            if constexpr (kPoisonLds) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) X[c][lane] = lds_poison_value();
+            }
             X[0][lane] = fm[1];
             X[1][lane] = fm[3];
             if (WX && wall_strip) {

@@ -303,6 +303,10 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
         // wave's next writes never reach a buffer another wave still reads.
         double(*XA)[TW] = xs[2 * (P & 1)];
         double(*XB)[TW] = xs[2 * (P & 1) + 1];
+        if constexpr (kPoisonLds) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) XA[c][lane] = XB[c][lane] = lds_poison_value();
+        }
         XA[0][lane] = fbp[1];
         XA[1][lane] = fbp[3];
         XA[2][lane] = fbp[6];
