@@ -33,14 +33,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_NODE = 160.0         # 10 FP64 planes read + 10 written per node and step
-# The three-pass step of a general (non-separable) mapping, per node: pass A reads f_hat and
-# writes f_bar^+ (160 B), pass B reads f_bar^+ and the 4 metric values and writes f(t+h)
-# (192 B), pass C reads f_hat, f(t+h) and the metric and writes f_hat(t+dt) (272 B).
-MAPPED_THREE_PASS_BYTES = 624.0
-# The three-pass step with a mass source and a force field on a uniform grid, per node: pass A
-# reads f_hat and R and writes f_bar^+ (168 B), pass B reads f_bar^+, R and (F_x, F_y) and writes
-# f(t+h) (184 B), pass C reads f_hat, f(t+h), R and the force and writes f_hat(t+dt) (264 B).
-SOURCE_THREE_PASS_BYTES = 616.0
+# The two-pass tiled step of a general (non-separable) mapping, per node: the half step reads
+# f_hat and the 4 metric values and writes f(t+h) (192 B; f_bar^+ is formed in LDS), the full
+# step reads f_hat, f(t+h) and the metric and writes f_hat(t+dt) (272 B).
+MAPPED_TILED_BYTES = 464.0
+# The same step with a mass source and a force field on a uniform grid, per node: the half step
+# reads f_hat, R and (F_x, F_y) and writes f(t+h) (184 B), the full step reads f_hat, f(t+h), R
+# and the force and writes f_hat(t+dt) (264 B).
+SOURCE_TILED_BYTES = 448.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2306_08216_amd", "csrc")
 TUNING = os.path.join(ROOT, "paper_2306_08216_amd", "tuning_mi355x.json")
@@ -260,7 +260,7 @@ def main():
     ap.add_argument("--seg-h", type=int, default=0,
                     help="rows per segment; -r: the balanced plan over r rounds of workgroups (0: library default)")
     ap.add_argument("--variant", type=int, default=-1,
-                    help="step kernel: 0 three-pass, 1 fused one wave per strip, 2 fused one wave per "
+                    help="step kernel: 0 tiled two-pass, 1 fused one wave per strip, 2 fused one wave per "
                          "velocity component (-1: the tuning cache's choice)")
     ap.add_argument("--cpu-serial-steps", type=int, default=2, help="oracle steps on one thread (0 = skip baseline)")
     ap.add_argument("--cpu-omp-steps", type=int, default=4, help="oracle steps per run on all cores")
@@ -322,7 +322,7 @@ def main():
             prerun = args.prerun
         elif args.workload == "trapezoid":
             prob = P.trapezoidal_cavity(n, re=100.0, lid=0.1)
-            wl = (f"lid-driven trapezoidal cavity Re 100 (general mapping, three-pass step), {n}x{n} nodes, "
+            wl = (f"lid-driven trapezoidal cavity Re 100 (general mapping, tiled step), {n}x{n} nodes, "
                   f"taper 0.4, lid 0.1, state pre-run {args.prerun} steps from rest, FP64")
             prerun = args.prerun
         else:
@@ -336,7 +336,7 @@ def main():
     nodes = sum(r["nodes"] for r in runs)
     ms_per_step = sum(r["ms_per_step"] for r in runs)     # one step of every run
     mlups = nodes / (ms_per_step / 1e3) / 1e6
-    bpn = MAPPED_THREE_PASS_BYTES if args.workload == "trapezoid" else BYTES_PER_NODE
+    bpn = MAPPED_TILED_BYTES if args.workload == "trapezoid" else BYTES_PER_NODE
     achieved = bpn * nodes / (ms_per_step / 1e3) / 1e9
     per_run = {}
     for r, prob in zip(runs, probs):
@@ -407,7 +407,7 @@ def main():
 def secondary_lines(args):
     """Context lines: the 1024^2 cavity (cache-resident pair), the batch, the
     trapezoidal cavity on a general mapping and the divergent flow with a mass
-    source (both on the three-pass step)."""
+    source (both on the tiled step)."""
     from paper_2306_08216_amd import problems as P
 
     class A:
@@ -428,18 +428,18 @@ def secondary_lines(args):
     a.steps, a.variant = min(args.steps, 500), 0
     prob = P.trapezoidal_cavity(2048, re=100.0, lid=0.1)
     r = run_solver(prob, a, "trapezoid2048", 1000)
-    gbs = MAPPED_THREE_PASS_BYTES * prob.nodes / (r["ms_per_step"] / 1e3) / 1e9
+    gbs = MAPPED_TILED_BYTES * prob.nodes / (r["ms_per_step"] / 1e3) / 1e9
     trap = {"workload": "lid-driven trapezoidal cavity Re 100 on a general (non-separable) mapping, 2048x2048, "
-                        "three-pass step (624 B per node: f_hat read twice, two intermediates written and read, "
-                        "the metric read twice)",
+                        "tiled step (464 B per node: f_hat read twice, f(t+h) written and read, the metric "
+                        "read twice)",
             "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "achieved_GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4), "steps": a.steps, "diagnostics": r["diagnostics"]}
     prob = P.divergent_flow(2048)
     r = run_solver(prob, a, "divergent2048", 200)
-    gbs = SOURCE_THREE_PASS_BYTES * prob.nodes / (r["ms_per_step"] / 1e3) / 1e9
+    gbs = SOURCE_TILED_BYTES * prob.nodes / (r["ms_per_step"] / 1e3) / 1e9
     src = {"workload": "steady divergent flow with a mass source R (eq. 2.1.1) and its balancing force field, "
-                       "periodic 2048x2048, three-pass step (616 B per node: f_hat read twice, two intermediates "
-                       "written and read, R read three times, the force field twice)",
+                       "periodic 2048x2048, tiled step (448 B per node: f_hat read twice, f(t+h) written "
+                       "and read, R and the force field read twice)",
            "mlups": round(r["mlups"], 2), "ms_per_step": r["ms_per_step"], "achieved_GBs": round(gbs, 1),
            "frac": round(gbs / HBM_PEAK_GBS, 4), "steps": a.steps, "diagnostics": r["diagnostics"]}
     return {"cavity1024": cav, "batch256": bat, "trapezoid2048": trap, "divergent2048": src}

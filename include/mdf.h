@@ -84,14 +84,14 @@ typedef struct {
      * upwinded by its own component's sign (Sec. 1 names the coordinate transformation and the
      * trapezoidal cavity; the formulas are this library's reading).  Walls lie on the index lines
      * i = 0, nx-1 and j = 0, ny-1.  Excludes inv_dx_x / inv_dx_y and needs dx_min > 0; the
-     * values must be finite with a non-zero Jacobian.  Runs on the three-pass step (variant 0)
+     * values must be finite with a non-zero Jacobian.  Runs on the tiled step (variant 0)
      * only; batches and the closure take no general mapping. */
     const double* metric;
     /* HOST, ny*nx values (x fastest), or NULL for R = 0: the mass source R of eq. 2.1.1 (the
      * alpha = 0 source of eq. 2.1.2), steady.  It enters the pressure of eq. 2.3.23, which on the
      * stored distributions phi = f + kappa Lambda~ (f - f^eq) becomes the plain sum plus
      * R (nu + kappa c_s^2)/2; the alpha = 0 equation itself is not carried (Remark 1).  Needs a
-     * Newtonian fluid (pl_n = 1) and finite values; runs on the three-pass step (variant 0) only;
+     * Newtonian fluid (pl_n = 1) and finite values; runs on the tiled step (variant 0) only;
      * batches take none. */
     const double* mass_source;
 } mdf_params;
@@ -156,7 +156,8 @@ mdf_status mdf_load(mdf_ctx* ctx, const double* f);
  * counter is kept.  Asynchronous on the context's stream. */
 mdf_status mdf_set_fields(mdf_ctx* ctx, const double* u0, const double* v0, const double* p0);
 
-/* Kernel selection for the time step: variant 0 = three-pass reference path,
+/* Kernel selection for the time step: variant 0 = tiled step (two tiled
+ * passes: Steps (1)-(3), then Step (4); any grid mapping and source),
  * 1 = fused single-pass strip kernel with one wave per strip (default for a
  * power-law fluid), 2 = fused single-pass strip kernel with one wave per
  * velocity component (default for a Newtonian fluid).
@@ -187,8 +188,8 @@ mdf_status mdf_set_partition_costs(mdf_ctx* ctx, double x_wall_scale, double y_w
  * depth (2, 3) and eight scalings (0.3..3.5) of the
  * wall-row cost factors of the one-round balanced partition over `steps`
  * steps of the run itself, times the three fastest again over 4 x `steps`
- * steps, restores the state and step count after each run (the three-pass
- * scratch of the workspace holds the copy), and keeps the fastest of the
+ * steps, restores the state and step count after each run (a spare state-sized
+ * buffer of the workspace holds the copy), and keeps the fastest of the
  * second timing.  choice (host, may be NULL; 6 doubles) receives {variant,
  * prefetch, x-wall scale, y-wall scale, milliseconds per step, tile_w}.
  * Synchronises.  Results do not depend on the choice (to rounding). */

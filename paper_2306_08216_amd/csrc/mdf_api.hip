@@ -554,7 +554,7 @@ mdf_status mdf_init(const mdf_params* p, const double* u0, const double* v0, con
     // allows, and there one wave per strip is faster.  A force field has
     // kernels of the second kind only.
     c->variant = (p->pl_n == 1.0 && !has_force_field(p)) ? 2 : 1;
-    // a general mapping and a mass source run on the three-pass step
+    // a general mapping and a mass source run on the tiled step
     if (p->metric || p->mass_source) c->variant = 0;
 
     // derivative scales 1/(X' dxi) per node (uniform: 1/dx)
@@ -695,7 +695,7 @@ mdf_status mdf_step(mdf_ctx* c, int64_t n)
         if (c->p.force_harmonic) set_force_time(c->K, c->p, c->steps);
         hipError_t e;
         if (c->variant == 0)
-            e = mdf::launch_three_pass(c->K, fin, c->fbp, c->fmid, fout, c->stream);
+            e = mdf::launch_tiled_step(c->K, fin, c->fmid, fout, c->stream);
         else if (c->variant == 1)
             e = mdf::launch_fused(c->K, c->shape, fin, fout, c->stream);
         else
@@ -831,14 +831,14 @@ mdf_status mdf_autotune(mdf_ctx* c, int32_t steps, double* choice)
 {
     if (!check_ctx(c)) return fail(nullptr, MDF_EINVAL, "ctx is NULL");
     if (steps < 1) return fail(c, MDF_EINVAL, "steps must be >= 1");
-    if (c->K.met || c->K.rsrc) {   // one step kernel (the three-pass step): nothing to choose
+    if (c->K.met || c->K.rsrc) {   // one step kernel (the tiled step): nothing to choose
         if (choice) {
             const double ch[6] = {0.0, (double)c->shape.prefetch, c->cx_scale, c->cy_scale, 0.0, (double)c->shape.tile_w};
             for (int k = 0; k < 6; ++k) choice[k] = ch[k];
         }
         return MDF_OK;
     }
-    // state backup in the three-pass scratch buffer (same size as a state buffer)
+    // state backup in the spare state-sized buffer of the workspace
     const size_t bytes = 10 * (size_t)c->K.pitch * (size_t)c->K.ny * sizeof(double);
     const int cur0 = c->cur;
     const int64_t steps0 = c->steps;

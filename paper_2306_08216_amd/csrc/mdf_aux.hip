@@ -1,6 +1,7 @@
 // Auxiliary kernels: initialisation, wall rule on a stored field, moments,
 // local derived quantities, diagnostics reductions, state copies, and the
-// three-pass reference time step (one kernel per sub-step of Sec. 2.2).
+// tiled time step (Steps (1)-(3) in one kernel, Step (4) in a second, wall
+// nodes after each).
 #include "mdf_device.hpp"
 #include "mdf_internal.hpp"
 
@@ -305,7 +306,7 @@ inline int perimeter_count(const StepConsts& K)
     return (K.bcy ? 2 * K.nx : 0) + (K.bcx ? 2 * (K.bcy ? K.ny - 2 : K.ny) : 0);
 }
 
-// ---- three-pass reference step ----
+// ---- tiled step ----
 
 // pressure offset of a stored form with coefficient r at node (x, y): SRC only
 template <bool SRC>
@@ -313,28 +314,6 @@ __device__ __forceinline__ double src_dp(const StepConsts& K, double r, int x, i
 {
     if constexpr (SRC) return r * source_at(K, x, y);
     return 0.0;
-}
-
-// pass A: f_bar^+ at every node (Step (1), eq. 2.2.15); wall nodes by the wall rule
-template <bool SRC>
-__global__ __launch_bounds__(256) void k_pass_a(StepConsts K, const double* __restrict__ fh, double* __restrict__ fbp)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= K.nx || y >= K.ny) return;
-    int x1, y1, x2, y2;
-    double uw, a[10], out[10];
-    if (wall_neighbours(K, x, y, x1, y1, x2, y2, uw)) {
-        double b[10], p1[10], p2[10];
-        load10(K, fh, x1, y1, a);
-        collide1_bar<SRC>(K, a, p1, src_dp<SRC>(K, K.r_hat, x1, y1));
-        load10(K, fh, x2, y2, b);
-        collide1_bar<SRC>(K, b, p2, src_dp<SRC>(K, K.r_hat, x2, y2));
-        wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, K.r_bp, x1, y1), src_dp<SRC>(K, K.r_bp, x2, y2));
-    } else {
-        load10(K, fh, x, y, a);
-        collide1_bar<SRC>(K, a, out, src_dp<SRC>(K, K.r_hat, x, y));
-    }
-    store10(K, fbp, x, y, out);
 }
 
 // Wall nodes of a field the tiled pass has just written at every interior
@@ -356,18 +335,22 @@ __global__ __launch_bounds__(256) void k_perimeter_wall(StepConsts K, double* __
     store10(K, f, x, y, out);
 }
 
-// ---- tiled sub-steps of the three-pass step (interior nodes) ----
+// ---- tiled sub-steps (interior nodes) ----
 // A 64 x 8 tile of nodes stages the moving components of its input field with a halo of 2 in LDS, so
 // each stencil value is loaded from memory once per tile instead of once per
 // use; the stencil then reads LDS.  Wall nodes are set afterwards from the
-// written interior (k_perimeter_wall).
+// written interior (k_perimeter_wall).  The half step computes its input,
+// f_bar^+, while it fills the tile (Step (1) at every tile and halo node,
+// from f_hat), so f_bar^+ never goes to memory.
 constexpr int TB_X = 64, TB_Y = 8, TB_HALO = 2;
 constexpr int TS_X = TB_X + 2 * TB_HALO, TS_Y = TB_Y + 2 * TB_HALO;
 
-// All 10 components of node (x, y) of a stored field for the tile: wrapped on
-// a periodic axis, the quadratic ghost one node beyond a wall; positions a
-// stencil never reads (further beyond a wall, or beyond two walls) get zeros.
-__device__ __forceinline__ void tile_node(const StepConsts& K, const double* f, int x, int y, double* phi)
+// All 10 components of node (x, y) of a field for the tile, node(x, y, phi)
+// giving them at a grid node: wrapped on a periodic axis, the quadratic ghost
+// one node beyond a wall; positions a stencil never reads (further beyond a
+// wall, or beyond two walls) get zeros.
+template <class Node>
+__device__ __forceinline__ void tile_node(const StepConsts& K, int x, int y, double* phi, Node node)
 {
     if (!K.bcx) x = ((x % K.nx) + K.nx) % K.nx;
     if (!K.bcy) y = ((y % K.ny) + K.ny) % K.ny;
@@ -378,7 +361,7 @@ __device__ __forceinline__ void tile_node(const StepConsts& K, const double* f, 
         return;
     }
     if (!out_x && !out_y) {
-        load_node(f, K.pitch, x, y, phi);
+        node(x, y, phi);
         return;
     }
     // one node beyond a wall: ghost from the wall node and the next two inward
@@ -388,9 +371,9 @@ __device__ __forceinline__ void tile_node(const StepConsts& K, const double* f, 
     if (y == -1) y0 = 0, dy = 1;
     if (y == K.ny) y0 = K.ny - 1, dy = -1;
     double a[10], b[10], c[10];
-    load_node(f, K.pitch, x0, y0, a);
-    load_node(f, K.pitch, x0 + dx, y0 + dy, b);
-    load_node(f, K.pitch, x0 + 2 * dx, y0 + 2 * dy, c);
+    node(x0, y0, a);
+    node(x0 + dx, y0 + dy, b);
+    node(x0 + 2 * dx, y0 + 2 * dy, c);
 #pragma unroll
     for (int q = 0; q < 10; ++q) phi[q] = ghost(a[q], b[q], c[q]);
 }
@@ -429,29 +412,103 @@ __device__ __forceinline__ double transport_tile(const StepConsts& K, const doub
 // or s + 2.
 __host__ __device__ constexpr int moving_slot(int q) { return q < 5 ? q - 1 : q - 2; }
 
-// FULL = false: pass B (half step of f_bar^+, then Step (3)) into f(t+h);
-// FULL = true: pass C (Step (4) on f(t+h) with f_hat^+ recomputed from f_hat).
+// FULL = false: pass B, src = f_hat: Step (1) into the tile, the half step of
+// f_bar^+, then Step (3), into f(t+h);
+// FULL = true: pass C, src = f(t+h): Step (4) with f_hat^+ recomputed from f_hat.
 template <bool FULL, bool SRC>
 __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const double* __restrict__ src,
                                                            const double* __restrict__ fh, double* __restrict__ dst)
 {
     __shared__ double tile[8][TS_Y][TS_X];
+    // pass B: f_bar^+ j = 0 of both sets at every tile position
+    __shared__ double rest[FULL ? 1 : 2][FULL ? 1 : TS_Y][FULL ? 1 : TS_X];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int ox = (int)blockIdx.x * TB_X - TB_HALO, oy = (int)blockIdx.y * TB_Y - TB_HALO;
     if constexpr (kPoisonLds) {
         for (int idx = ty * TB_X + tx; idx < 8 * TS_X * TS_Y; idx += TB_X * TB_Y)
             (&tile[0][0][0])[idx] = lds_poison_value();
+        if constexpr (!FULL)
+            for (int idx = ty * TB_X + tx; idx < 2 * TS_X * TS_Y; idx += TB_X * TB_Y)
+                (&rest[0][0][0])[idx] = lds_poison_value();
         __syncthreads();
     }
     for (int idx = ty * TB_X + tx; idx < TS_X * TS_Y; idx += TB_X * TB_Y) {
         const int ly = idx / TS_X, lx = idx - ly * TS_X;
         double phi[10];
-        tile_node(K, src, ox + lx, oy + ly, phi);
+        if constexpr (FULL) {
+            tile_node(K, ox + lx, oy + ly, phi, [&](int x, int y, double* o) { load_node(src, K.pitch, x, y, o); });
+        } else {
+            // Step (1) at the interior nodes; wall nodes and the ghosts beyond
+            // them follow from the tile below
+            int x = ox + lx, y = oy + ly;
+            if (!K.bcx) x = ((x % K.nx) + K.nx) % K.nx;
+            if (!K.bcy) y = ((y % K.ny) + K.ny) % K.ny;
+            if (x >= 0 && x < K.nx && y >= 0 && y < K.ny && !is_wall(K, x, y)) {
+                double a[10];
+                load10(K, src, x, y, a);
+                collide1_bar<SRC>(K, a, phi, src_dp<SRC>(K, K.r_hat, x, y));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 10; ++q) phi[q] = 0.0;
+            }
+            rest[0][ly][lx] = phi[0];
+            rest[FULL ? 0 : 1][ly][lx] = phi[5];
+        }
 #pragma unroll
         for (int q = 0; q < 10; ++q)
             if (q % 5 != 0) tile[moving_slot(q)][ly][lx] = phi[q];
     }
     __syncthreads();
+    if constexpr (!FULL) {
+        // A tile that holds wall nodes (uniform over the workgroup).  Their
+        // inward neighbours are interior nodes of the same tile (grids have at
+        // least 5 nodes per axis), so the wall rule takes their f_bar^+ from
+        // LDS; then the ghost one node beyond a wall is the quadratic
+        // extrapolation from the wall node and the next two inward nodes
+        // (positions beyond two walls stay zero).
+        const bool edge = (K.bcx && (ox <= 0 || ox + TS_X >= K.nx)) || (K.bcy && (oy <= 0 || oy + TS_Y >= K.ny));
+        if (edge) {
+            auto at = [&](int lx, int ly, double* o) {
+#pragma unroll
+                for (int q = 0; q < 10; ++q)
+                    o[q] = q % 5 == 0 ? rest[FULL ? 0 : q / 5][ly][lx] : tile[moving_slot(q)][ly][lx];
+            };
+            for (int idx = ty * TB_X + tx; idx < TS_X * TS_Y; idx += TB_X * TB_Y) {
+                const int ly = idx / TS_X, lx = idx - ly * TS_X;
+                int x = ox + lx, y = oy + ly;
+                if (!K.bcx) x = ((x % K.nx) + K.nx) % K.nx;
+                if (!K.bcy) y = ((y % K.ny) + K.ny) % K.ny;
+                int x1, y1, x2, y2;
+                double uw;
+                if (x < 0 || x >= K.nx || y < 0 || y >= K.ny || !wall_neighbours(K, x, y, x1, y1, x2, y2, uw))
+                    continue;
+                double p1[10], p2[10], out[10];
+                at(lx + (x1 - x), ly + (y1 - y), p1);
+                at(lx + (x2 - x), ly + (y2 - y), p2);
+                wall_extrapolate<SRC>(K, p1, p2, uw, out, src_dp<SRC>(K, K.r_bp, x1, y1),
+                                      src_dp<SRC>(K, K.r_bp, x2, y2));
+                rest[0][ly][lx] = out[0];
+                rest[FULL ? 0 : 1][ly][lx] = out[5];
+#pragma unroll
+                for (int q = 0; q < 10; ++q)
+                    if (q % 5 != 0) tile[moving_slot(q)][ly][lx] = out[q];
+            }
+            __syncthreads();
+            for (int idx = ty * TB_X + tx; idx < TS_X * TS_Y; idx += TB_X * TB_Y) {
+                const int ly = idx / TS_X, lx = idx - ly * TS_X;
+                const int x = ox + lx, y = oy + ly;
+                const bool ox_ = K.bcx && (x == -1 || x == K.nx), oy_ = K.bcy && (y == -1 || y == K.ny);
+                const bool in_x = !K.bcx || (x >= 0 && x < K.nx), in_y = !K.bcy || (y >= 0 && y < K.ny);
+                if (!((ox_ && in_y) || (oy_ && in_x))) continue;
+                const int dx = ox_ ? (x == -1 ? 1 : -1) : 0, dy = oy_ ? (y == -1 ? 1 : -1) : 0;
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    tile[s][ly][lx] = ghost(tile[s][ly + dy][lx + dx], tile[s][ly + 2 * dy][lx + 2 * dx],
+                                            tile[s][ly + 3 * dy][lx + 3 * dx]);
+            }
+            __syncthreads();
+        }
+    }
     const int x = (int)blockIdx.x * TB_X + tx, y = (int)blockIdx.y * TB_Y + ty;
     if (x >= K.nx || y >= K.ny || is_wall(K, x, y)) return;
     const int cx = tx + TB_HALO, cy = ty + TB_HALO;
@@ -462,7 +519,8 @@ __global__ __launch_bounds__(TB_X* TB_Y) void k_pass_tiled(StepConsts K, const d
         collide1_hat<SRC>(K, a, base, src_dp<SRC>(K, K.r_hat, x, y));
     } else {
 #pragma unroll
-        for (int q = 0; q < 10; ++q) base[q] = q % 5 == 0 ? comp(K, src, x, y, q) : tile[moving_slot(q)][cy][cx];
+        for (int q = 0; q < 10; ++q)
+            base[q] = q % 5 == 0 ? rest[FULL ? 0 : q / 5][FULL ? 0 : cy][FULL ? 0 : cx] : tile[moving_slot(q)][cy][cx];
     }
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
@@ -572,12 +630,11 @@ hipError_t launch_unpack(const StepConsts& K, const double* dense, double* f, hi
 
 namespace {
 template <bool SRC>
-void three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew, hipStream_t s)
+void tiled_step(const StepConsts& K, const double* fh, double* fmid, double* fnew, hipStream_t s)
 {
-    const dim3 b(64, 4), bt(TB_X, TB_Y);
+    const dim3 bt(TB_X, TB_Y);
     const int nper = perimeter_count(K);
-    hipLaunchKernelGGL(k_pass_a<SRC>, grid2d(K, b), b, 0, s, K, fh, fbp);
-    hipLaunchKernelGGL((k_pass_tiled<false, SRC>), grid2d(K, bt), bt, 0, s, K, fbp, nullptr, fmid);
+    hipLaunchKernelGGL((k_pass_tiled<false, SRC>), grid2d(K, bt), bt, 0, s, K, fh, nullptr, fmid);
     if (nper > 0) hipLaunchKernelGGL(k_perimeter_wall<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fmid, K.r_f);
     hipLaunchKernelGGL((k_pass_tiled<true, SRC>), grid2d(K, bt), bt, 0, s, K, fmid, fh, fnew);
     if (nper > 0) hipLaunchKernelGGL(k_perimeter_wall<SRC>, dim3((nper + 255) / 256), dim3(256), 0, s, K, fnew, K.r_hat);
@@ -586,13 +643,12 @@ void three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid
 
 // the kernels with the mass source's pressure offsets are separate instances,
 // so a run without source executes exactly the plain step
-hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew,
-                             hipStream_t s)
+hipError_t launch_tiled_step(const StepConsts& K, const double* fh, double* fmid, double* fnew, hipStream_t s)
 {
     if (K.rsrc)
-        three_pass<true>(K, fh, fbp, fmid, fnew, s);
+        tiled_step<true>(K, fh, fmid, fnew, s);
     else
-        three_pass<false>(K, fh, fbp, fmid, fnew, s);
+        tiled_step<false>(K, fh, fmid, fnew, s);
     return hipGetLastError();
 }
 

@@ -21,8 +21,7 @@ hipError_t launch_pack(const StepConsts& K, const double* f, double* dense, hipS
 // streaming copy of bytes (a multiple of 16) with 16-byte loads and stores
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_unpack(const StepConsts& K, const double* dense, double* f, hipStream_t s);
-hipError_t launch_three_pass(const StepConsts& K, const double* fh, double* fbp, double* fmid, double* fnew,
-                             hipStream_t s);
+hipError_t launch_tiled_step(const StepConsts& K, const double* fh, double* fmid, double* fnew, hipStream_t s);
 
 // Fused single-pass step: strips of tile_w lanes (one column each, 8 halo
 // columns) marching over row segments.  Segments are either seg_h rows each

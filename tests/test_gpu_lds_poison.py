@@ -2,7 +2,7 @@
 sets every LDS slot to NaN before a kernel publishes in it, so a read of a
 slot that no thread wrote for the current row or tile puts a NaN into the
 state.  The parity cases below (both fused variants at every tile width,
-walls on both axes, the power law, the three-pass step on general mappings,
+walls on both axes, the power law, the tiled step on general mappings,
 the batch and the diagnostics) must still match the oracle to 1e-12.
 
 The checking build runs in a child process (the environment variable
@@ -43,9 +43,9 @@ def worker():
         ("power law n = 0.5, 64 lanes", pl(48, 0.5), 80, (1, 64, 0, 2)),
         ("power law n = 1.5, 256 lanes", pl(300, 1.5), 30, (1, 256, 0, 2)),
         ("four-roll mill (force field)", P.four_roll_mill(40), 100, (1, 64, 0, 2)),
-        ("cavity40 three-pass", P.cavity(40, re=100.0), 100, (0, 0, 0, 0)),
-        ("warped Taylor-Green three-pass", P.warped_taylor_green(40, shear=1, eps=0.2), 100, (0, 0, 0, 0)),
-        ("trapezoid three-pass", P.trapezoidal_cavity(48), 100, (0, 0, 0, 0)),
+        ("cavity40 tiled step", P.cavity(40, re=100.0), 100, (0, 0, 0, 0)),
+        ("warped Taylor-Green tiled step", P.warped_taylor_green(40, shear=1, eps=0.2), 100, (0, 0, 0, 0)),
+        ("trapezoid tiled step", P.trapezoidal_cavity(48), 100, (0, 0, 0, 0)),
         ("divergent channel (mass source)", P.divergent_channel(40), 100, (0, 0, 0, 0)),
     ]
     bad = 0

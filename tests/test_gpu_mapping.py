@@ -110,7 +110,7 @@ def test_general_mapping_parity(gpu, key):
 def test_identity_mapping_reproduces_the_separable_step(gpu):
     """The general transport with the metric of a uniform grid (d i/dx = d j/dy
     = 1/dx, the cross terms 0) computes the same products as the separable
-    three-pass step; only the compiler's fusing of subtractions into
+    tiled step; only the compiler's fusing of subtractions into
     multiply-adds differs, so after 100 steps the two agree to rounding
     (1e-14 of the largest value; measured 1.2e-15)."""
     ident = P.taylor_green(32)
@@ -130,7 +130,7 @@ def test_identity_mapping_reproduces_the_separable_step(gpu):
 
 
 def test_general_mapping_kernel_limits(gpu):
-    """A general mapping runs on the three-pass step: the fused kernels are
+    """A general mapping runs on the tiled step: the fused kernels are
     rejected and the autotuner reports variant 0 without changing the state."""
     from paper_2306_08216_amd._lib import MdfError
     o, prob, steps = oracle_run("warped_tg40")

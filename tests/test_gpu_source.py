@@ -122,8 +122,8 @@ def test_source_follows_the_closed_form_on_the_gpu(gpu):
     assert gre < 1.2e-2
 
 
-def test_zero_source_matches_the_plain_three_pass_step(gpu):
-    """R = 0 everywhere through the source kernels gives the plain three-pass
+def test_zero_source_matches_the_plain_tiled_step(gpu):
+    """R = 0 everywhere through the source kernels gives the plain tiled
     step exactly (the offsets add zero)."""
     prob = P.cavity(40, re=100.0)
     a = gpu(prob, device="cuda:0")
@@ -141,7 +141,7 @@ def test_zero_source_matches_the_plain_three_pass_step(gpu):
 
 def test_mass_source_full_size(gpu):
     """512^2 divergent flow, 3 steps, in the launch configuration of every run
-    with a source (the three-pass step), against the oracle on every node."""
+    with a source (the tiled step), against the oracle on every node."""
     from oracle.orc import Oracle
     prob = P.divergent_flow(512)
     say("[gpu source] divergent512 steps=3")
@@ -157,7 +157,7 @@ def test_mass_source_full_size(gpu):
 
 
 def test_mass_source_kernel_limits(gpu):
-    """A run with a source has the three-pass step only: the fused kernels are
+    """A run with a source has the tiled step only: the fused kernels are
     rejected and the autotuner reports variant 0 without changing the state."""
     from paper_2306_08216_amd._lib import MdfError
     o, prob, steps = oracle_run("divergent32")
