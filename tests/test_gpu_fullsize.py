@@ -47,10 +47,10 @@ def _wall_field(n, seed, amp):
     return u, v
 
 
-def _check_tuned(Solver, prob, steps, label):
+def _check_tuned(Solver, prob, steps, label, cache=TUNING):
     from oracle.orc import Oracle
     s = Solver(prob, device="cuda:0")
-    choice, cached = s.tuned(TUNING, steps=10)
+    choice, cached = s.tuned(cache, steps=10)
     say(f"[gpu full-size] {label}: choice={choice} from_cache={cached}, {steps} steps")
     assert s.steps == 0
     s.step(steps)
@@ -119,3 +119,23 @@ def test_powerlaw_2048_sheared_state(gpu, pl_n):
     # is the state tolerance relative to the local magnitude (a few ulps).
     assert np.all(d <= TOL * np.maximum(1.0, np.abs(fo)))
     del torch
+
+
+def test_trapezoid_2048_tiled_step(gpu):
+    """The benchmark's general-mapping workload at its own size: the 2048^2
+    trapezoidal cavity on its body-fitted grid (tiled step, the only kernel
+    for a general mapping, chosen without timing and not cached), from a
+    sheared state, against the oracle."""
+    prob = P.trapezoidal_cavity(2048, re=100.0, lid=0.1)
+    prob.u0, prob.v0 = _wall_field(2048, 21, 0.02)
+    choice = _check_tuned(gpu, prob, 3, "trapezoidal cavity 2048^2 (tiled step)", cache=None)
+    assert choice[0] == 0
+
+
+def test_divergent_flow_2048_tiled_step(gpu):
+    """The benchmark's mass-source workload at its own size: the periodic
+    2048^2 divergent flow with its force field (tiled step), against the
+    oracle."""
+    prob = P.divergent_flow(2048)
+    choice = _check_tuned(gpu, prob, 3, "divergent flow 2048^2 (tiled step)", cache=None)
+    assert choice[0] == 0
