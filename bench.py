@@ -46,6 +46,7 @@ CSRC = os.path.join(ROOT, "paper_2306_08216_amd", "csrc")
 TUNING = os.path.join(ROOT, "paper_2306_08216_amd", "tuning_mi355x.json")
 METRIC = "MLUPS (FP64) + % HBM roofline; learned-closure speedup at equal L2 error"
 REGIONS = 5
+SETTLE = 300                   # last pre-run steps, run after the host copy of the state (see run_solver)
 
 
 def log(*a):
@@ -166,12 +167,17 @@ def fail_diverged(what, diag, status):
 def run_solver(prob, args, label, prerun, want_state=False):
     """Set up one run, pre-run and warm it up, take the kernel choice (tuning
     cache or autotuner, outside the timing), time exactly args.steps steps.
-    Returns a dict of results (and the state before the timed steps)."""
+    Returns a dict of results (and the state SETTLE steps before the warm-up)."""
     import torch
     from paper_2306_08216_amd.solver import Solver
     s = Solver(prob, device="cuda:0")
-    s.step(prerun)
-    s.step(args.warmup)
+    # The pre-run ends on the chosen kernel with no host work in between: after
+    # an idle gap of some milliseconds (the host copy of the state, a sleep)
+    # the step runs up to 20 % slower for about 80 steps before it returns to
+    # its steady rate, so the CPU baseline's copy of the state is taken
+    # SETTLE steps before the warm-up, not just before the timed steps.
+    settle = min(prerun, SETTLE)
+    s.step(prerun - settle)
     torch.cuda.synchronize()
     if args.variant >= 0 or args.tile_w or args.seg_h or args.prefetch or args.cost_scales:
         variant = args.variant if args.variant >= 0 else (1 if prob.pl_n != 1.0 else 2)
@@ -188,6 +194,8 @@ def run_solver(prob, args, label, prerun, want_state=False):
         tuned = {"variant": int(choice[0]), "tile_w": int(choice[1]), "prefetch": int(choice[2]),
                  "x_wall_cost_scale": choice[3], "y_wall_cost_scale": choice[4], "from_cache": cached}
     state = s.save().cpu().numpy() if want_state else None
+    s.step(settle)
+    s.step(args.warmup)
     s.step(5)   # first launches of the chosen kernel outside the timing
     t0 = time.perf_counter()
     ms = time_regions(s.step, s.stream, args.steps)
@@ -212,7 +220,7 @@ def cpu_baseline(probs_states, serial_steps, omp_steps):
     """The oracle as it stands on the same workload: `serial_steps` steps of the
     first problem on one thread, then `omp_steps` steps of every problem on
     the OpenMP build of the same source over all host cores, each from the
-    GPU's state before the timed region."""
+    GPU's state of the same run, taken SETTLE steps before the warm-up."""
     from oracle.orc import Oracle
     cores = os.cpu_count() or 1
     p0, f0 = probs_states[0]
@@ -238,7 +246,7 @@ def cpu_baseline(probs_states, serial_steps, omp_steps):
             "single_thread": {"value": round(serial, 4), "unit": "MLUPS", "cores": 1, "seconds": round(t_serial, 2)},
             "sample": (f"{omp_steps} step(s) of each of the {len(probs_states)} timed runs on the OpenMP build "
                        f"({threads} threads, {t_omp:.1f} s) and {serial_steps} step(s) of the first on the "
-                       f"sequential build ({t_serial:.1f} s), both from the GPU's state before the timed steps; "
+                       f"sequential build ({t_serial:.1f} s), both from the GPU's state {SETTLE} steps before the warm-up; "
                        f"C oracle, -O2 -ffp-contract=off")}
 
 
