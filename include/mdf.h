@@ -236,7 +236,9 @@ mdf_status mdf_cnn_forward(void* ws, size_t ws_bytes, const float* params, int32
  * as mdf_cnn_forward; calls no allocator.  Every call on a GPU shares that
  * GPU's array, so calls that overlap on one GPU (other streams, other host
  * threads) race; the array keeps the last call's contents, none of which a
- * call reads before writing it.  Asynchronous on hip_stream. */
+ * call reads before writing it.  The array used is that of the device that
+ * runs hip_stream (the current device for the null stream).  Asynchronous on
+ * hip_stream. */
 #define MDF_CNN_NOALLOC_MAX_PIXELS 16384
 mdf_status mdf_cnn_forward_noalloc(const float* params, int32_t batch, int32_t h, int32_t w, const double* uv,
                                    double in_scale, double out_scale, double* duv, void* hip_stream);

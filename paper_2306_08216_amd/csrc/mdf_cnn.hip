@@ -597,16 +597,30 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
 void* g_scratch_ptr[kMaxDevices] = {};
 
-hipError_t scratch_address(void** out)
+// The copy of the device that runs `s` (the current device for the null
+// stream); its address is looked up the first time with that device current.
+hipError_t scratch_address(hipStream_t s, void** out)
 {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return e;
+    int dev = cur;
+    if (s) {
+        hipDevice_t sd = 0;
+        e = hipStreamGetDevice(s, &sd);
+        if (e != hipSuccess) return e;
+        dev = (int)sd;
+    }
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lock(g_scratch_mutex);
     if (!g_scratch_ptr[dev]) {
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
         void* p = nullptr;
         e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) {
+            const hipError_t r = hipSetDevice(cur);
+            if (e == hipSuccess) e = r;
+        }
         if (e != hipSuccess) return e;
         g_scratch_ptr[dev] = p;
     }
@@ -632,7 +646,7 @@ hipError_t cnn_forward_noalloc(const float* params, int B, int H, int W, const d
     const CnnLayout L = cnn_layout(B, H, W, false);
     if (L.total > kNoAllocBytes) return hipErrorInvalidValue;
     void* ws = nullptr;
-    const hipError_t e = scratch_address(&ws);
+    const hipError_t e = scratch_address(s, &ws);
     if (e != hipSuccess) return e;
     return forward_at(L, (char*)ws, params, B, H, W, uv, in_scale, out_scale, duv, s);
 }
