@@ -139,3 +139,39 @@ def test_divergent_flow_2048_tiled_step(gpu):
     prob = P.divergent_flow(2048)
     choice = _check_tuned(gpu, prob, 3, "divergent flow 2048^2 (tiled step)", cache=None)
     assert choice[0] == 0
+
+
+_PL256 = {}
+
+
+def _oracle_pl256(pl_n, steps):
+    """The oracle's state after `steps` steps of the 256^2 power-law cavity, computed once per index."""
+    from oracle.orc import Oracle
+    if pl_n not in _PL256:
+        o = Oracle(P.powerlaw_cavity(256, pl_n=pl_n), threads=THREADS)
+        o.step(steps)
+        _PL256[pl_n] = o.f()
+    return _PL256[pl_n]
+
+
+@pytest.mark.parametrize("pl_n", [0.5, 1.5])
+@pytest.mark.parametrize("shape", [(256, 2), (64, 2), (128, 3)])
+def test_powerlaw_256_from_rest_500_steps(gpu, pl_n, shape):
+    """The power-law configuration's own parity case: the tanh-stretched cavity
+    at 256^2 from rest, 500 steps at its own clamps ([1e-2, 1e2] nu_ref for
+    n = 0.5, [1e-2, 4] nu_ref for n = 1.5), on the benchmark's kernel shape
+    (256-lane strips, prefetch 2) and on two others."""
+    tw, pf = shape
+    prob = P.powerlaw_cavity(256, pl_n=pl_n)
+    s = gpu(prob, device="cuda:0")
+    s.set_kernel(1, tw, 0, pf)
+    say(f"[gpu parity] power-law n={pl_n} 256^2 from rest, 500 steps, {tw} lanes, prefetch {pf}")
+    s.step(500)
+    f = s.save().cpu().numpy()
+    s.close()
+    fo = _oracle_pl256(pl_n, 500)
+    d = np.abs(f - fo)
+    say(f"    max|df|={d.max():.3e} max|f|={np.abs(fo).max():.3e}")
+    assert np.all(np.isfinite(f))
+    # where the lid corners hold |f| above 1 (n = 1.5) the bar is relative
+    assert np.all(d <= TOL * np.maximum(1.0, np.abs(fo)))
