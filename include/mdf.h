@@ -201,7 +201,11 @@ mdf_status mdf_autotune(mdf_ctx* ctx, int32_t steps, double* choice);
  * writes (strip, first row, end row) triples to out[3*i..3*i+2], strips
  * being the tile_w-8 column slices of the grid (tile_w 64, 128 or 256 for
  * variant 1; variant 2 always uses 64), and returns the number of segments,
- * or 0 for invalid input or when cap is too small.  No device work. */
+ * or 0 for invalid input or when cap is too small.  No device work.  On a
+ * grid with x walls, variant 1 at 128 or 256 lanes does not launch this
+ * plan once the grid is at least 128 columns wide: it runs the 56 columns
+ * next to each x wall as single-wave tasks, several to a workgroup, and
+ * cuts only the columns between them into strips. */
 int32_t mdf_plan_segments(const mdf_params* p, int32_t variant, int32_t tile_w, int32_t slots, int32_t* out,
                           int32_t cap);
 

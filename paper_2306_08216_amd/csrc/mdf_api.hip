@@ -296,6 +296,103 @@ int balanced_partition(int nx, int ny, bool wall_x, bool wall_y, int tile_w, int
     return balanced_partition_multi(&g, 1, tile_w, slots, cx, cy, out, cap);
 }
 
+bool wall_tasks_apply(int nx, bool wall_x, int tile_w)
+{
+    return wall_x && tile_w > 64 && nx - 2 * kWallCols >= 16;
+}
+
+namespace {
+// Plan at budget T with wall tasks: the columns [W, nx - W) (W = kWallCols) cut
+// into strips of tile_w lanes, each segmented at cost 1 (cy next to a y wall),
+// and the two W-column strips at the x walls cut into single-wave tasks at
+// cost cx.  Writes the workgroup entries to out[0, nwg) -- interior segments
+// (strip, ys0, ys1, 0), then (-1 - j, 0, 0, 0) for each group j of tile_w/64
+// tasks -- and the tasks (xs0, xs1, ys0, ys1) to out[nwg + j tile_w/64 + w],
+// empty ones (0, 0, 0, 0).  Returns nwg (entries nwg + groups*tile_w/64 in
+// *total), or -1 if some segment cannot hold a row.
+int plan_wall_tasks(int nx, int ny, bool wall_y, int tile_w, double cx, double cy, double T, int4* out, int cap,
+                    int* total)
+{
+    constexpr int W = kWallCols;
+    auto rows_for = [](double budget) { return ((int)std::floor(budget) & ~3) - 8; };
+    const int span = nx - 2 * W, tpw = tile_w / 64;
+    const int nstrips = (span + tile_w - 9) / (tile_w - 8);
+    // segments of one column range at factor fx: calls emit(ys0, ys1)
+    auto cut = [&](double fx, auto emit) -> bool {
+        int y = 0;
+        while (y < ny) {
+            int h = rows_for(T / (fx * ((wall_y && y <= 8) ? cy : 1.0)));
+            if (wall_y && y + h >= ny - 8) h = rows_for(T / (fx * cy));   // ends next to the top wall
+            if (h < 1) return false;
+            if (y + h > ny) h = ny - y;
+            emit(y, y + h);
+            y += h;
+        }
+        return true;
+    };
+    int nint = 0;
+    for (int st = 0; st < nstrips; ++st)
+        if (!cut(1.0, [&](int a, int b) {
+                if (out && nint < cap) out[nint] = make_int4(st, a, b, 0);
+                ++nint;
+            }))
+            return -1;
+    // the tasks, in order: left wall strip, then right
+    int ntask = 0;
+    int4* tasks = nullptr;
+    const int tcap = 2 * (ny + 1);
+    if (out) tasks = new (std::nothrow) int4[tcap];
+    if (out && !tasks) return -1;
+    for (int side = 0; side < 2; ++side) {
+        const int x0 = side == 0 ? 0 : nx - W, x1 = side == 0 ? W : nx;
+        if (!cut(cx, [&](int a, int b) {
+                if (tasks && ntask < tcap) tasks[ntask] = make_int4(x0, x1, a, b);
+                ++ntask;
+            })) {
+            delete[] tasks;
+            return -1;
+        }
+    }
+    const int groups = (ntask + tpw - 1) / tpw, nwg = nint + groups;
+    *total = nwg + groups * tpw;
+    if (out && *total <= cap) {
+        for (int j = 0; j < groups; ++j) {
+            out[nint + j] = make_int4(-1 - j, 0, 0, 0);
+            for (int w = 0; w < tpw; ++w) {
+                const int i = j * tpw + w;
+                out[nwg + i] = i < ntask ? tasks[i] : make_int4(0, 0, 0, 0);
+            }
+        }
+    }
+    delete[] tasks;
+    return nwg;
+}
+}  // namespace
+
+int balanced_partition_wall_tasks(int nx, int ny, bool wall_y, int tile_w, int slots, double cx, double cy, int4* out,
+                                  int cap, int* total)
+{
+    double lo = 9.0, hi = cx * cy * (ny + 12) + 1.0;   // hi: one segment per strip and wall strip
+    int tot = 0;
+    if (plan_wall_tasks(nx, ny, wall_y, tile_w, cx, cy, hi, nullptr, 0, &tot) > slots) {
+        lo = hi;
+    } else {
+        while (hi - lo > 0.25) {
+            const double mid = 0.5 * (lo + hi);
+            const int n = plan_wall_tasks(nx, ny, wall_y, tile_w, cx, cy, mid, nullptr, 0, &tot);
+            if (n > 0 && n <= slots)
+                hi = mid;
+            else
+                lo = mid;
+        }
+        lo = hi;
+    }
+    const int n = plan_wall_tasks(nx, ny, wall_y, tile_w, cx, cy, lo, out, cap, &tot);
+    if (n <= 0 || tot > cap) return 0;
+    *total = tot;
+    return n;
+}
+
 }  // namespace mdf
 
 namespace {
@@ -311,6 +408,8 @@ mdf::FusedShape default_shape()
 // wall (cy), measured on MI355X for each fused kernel against its wall-free
 // march (lid-driven cavity 1024^2): the wall rule, the ghost nodes and the
 // divergent lanes of the x-wall strips make those rows dearer.
+constexpr double kWallTaskCost = 2.48;   // row cost of a single-wave task at an x wall
+
 void segment_costs(int variant, double& cx, double& cy)
 {
     if (variant == 1) {
@@ -329,24 +428,34 @@ mdf_status prepare_shape(mdf_ctx* c)
     if (c->variant == 0 || sh.seg_h > 0) {
         sh.table = nullptr;
         sh.nwg = 0;
+        sh.wall_tasks = 0;
         return MDF_OK;
     }
+    // the per-component kernel always runs 64-lane strips; a 128-lane strip
+    // takes two waves, so a round holds half as many of its workgroups
+    const int tw = c->variant == 2 ? 64 : sh.tile_w;
+    const bool tasks = c->variant == 1 && mdf::wall_tasks_apply(c->p.nx, c->p.bc_x == MDF_BC_WALL, tw);
     double cx, cy;
     segment_costs(c->variant, cx, cy);
+    // a single-wave task at an x wall: one wave (64 lanes, 8 of them halo) per
+    // row instead of four, so it takes longer per row than a wall strip of
+    // four waves (2.48x an interior row; measured over scales of the factor)
+    if (tasks) cx = kWallTaskCost;
     cx = 1.0 + (cx - 1.0) * c->cx_scale;
     cy = 1.0 + (cy - 1.0) * c->cy_scale;
     int4* host = new (std::nothrow) int4[kSegCap];
     if (!host) return fail(c, MDF_EDEVICE, "out of host memory");
-    // the per-component kernel always runs 64-lane strips; a 128-lane strip
-    // takes two waves, so a round holds half as many of its workgroups
-    const int tw = c->variant == 2 ? 64 : sh.tile_w;
     const int want = c->slots * c->rounds / (tw / 64);
     const int slots = want < kSegCap ? want : kSegCap;
-    const int n = mdf::balanced_partition(c->p.nx, c->p.ny, c->p.bc_x == MDF_BC_WALL, c->p.bc_y == MDF_BC_WALL, tw,
-                                          slots, cx, cy, host, kSegCap);
+    int total = 0;
+    const int n = tasks ? mdf::balanced_partition_wall_tasks(c->p.nx, c->p.ny, c->p.bc_y == MDF_BC_WALL, tw, slots, cx,
+                                                             cy, host, kSegCap, &total)
+                        : mdf::balanced_partition(c->p.nx, c->p.ny, c->p.bc_x == MDF_BC_WALL,
+                                                  c->p.bc_y == MDF_BC_WALL, tw, slots, cx, cy, host, kSegCap);
+    if (!tasks) total = n;
     hipError_t e = hipSuccess;
     if (n > 0) {
-        e = hipMemcpyAsync(c->seg, host, sizeof(int4) * n, hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->seg, host, sizeof(int4) * total, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
     delete[] host;
@@ -354,6 +463,7 @@ mdf_status prepare_shape(mdf_ctx* c)
     if (e != hipSuccess) return hip_check(c, e, "segment table upload");
     sh.table = c->seg;
     sh.nwg = n;
+    sh.wall_tasks = tasks ? 1 : 0;
     return MDF_OK;
 }
 

@@ -47,7 +47,10 @@ hipError_t launch_fused(const StepConsts& K, FusedShape sh, const double* fin, d
 {
     fusedk::FusedGrid G;
     const int wout = sh.tile_w - 8;
-    G.nstrips = (K.nx + wout - 1) / wout;
+    const bool tasks = sh.wall_tasks && sh.seg_h <= 0;
+    G.xoff = tasks ? kWallCols : 0;
+    G.xspan = tasks ? K.nx - 2 * kWallCols : K.nx;
+    G.nstrips = (G.xspan + wout - 1) / wout;
     if (sh.seg_h > 0) {
         G.nsegs = (K.ny + sh.seg_h - 1) / sh.seg_h;
         G.nwg = G.nstrips * G.nsegs;

@@ -33,6 +33,11 @@ namespace fusedk {
 struct FusedGrid {
     int nstrips, nsegs, chunk, nwg;
     const int4* table;   // (strip, ys0, ys1, 0) per workgroup, or null: nsegs equal segments per strip
+    // Strip s covers columns xoff + s*xspan/nstrips .. xoff + (s+1)*xspan/nstrips - 1.  With
+    // wall tasks (xoff = kWallCols) the columns next to each x wall are not cut into strips:
+    // table entries (-1 - j, 0, 0, 0) run TW/64 single-wave tasks (xs0, xs1, ys0, ys1) read
+    // from table[nwg + j*TW/64 + wave].
+    int xoff, xspan;
 };
 
 // equilibrium component (velocity along the wall normal axis) used by the wall
@@ -113,9 +118,8 @@ __device__ __forceinline__ void x_neighbours(const StepConsts& K, double (*X)[TW
 template <int TW, bool WX, bool WY, int PLK, int PF, bool UNI, bool FF>
 __device__ __forceinline__ void fused_march(const StepConsts& K, const double* __restrict__ fin,
                                             double* __restrict__ fout, const double* __restrict__ gyp, int xs0,
-                                            int xs1, int ys0, int ys1, double (*xs)[9][TW])
+                                            int xs1, int ys0, int ys1, double (*xs)[9][TW], int lane)
 {
-    const int lane = threadIdx.x;
     const int x = xs0 - 4 + lane;
     int xg;
     if (WX) {
@@ -483,6 +487,29 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
     }
 }
 
+// One single-wave task (xs0, xs1, ys0, ys1) of a workgroup of TW lanes: a 64-lane march on
+// this wave's quarter of the workgroup's exchange buffers, with wave barriers only, so the
+// wave runs at its own pace.  An empty task (xs0 >= xs1) returns at once.
+template <int TW, bool WY, int PLK, int PF, bool UNI, bool FF>
+__device__ __forceinline__ void wall_tasks(const StepConsts& K, const double* __restrict__ fin,
+                                           double* __restrict__ fout, const double* __restrict__ gyp, int4 t,
+                                           double (*xs)[9][TW])
+{
+    if (t.x >= t.y) return;
+    double(*xw)[9][64] = reinterpret_cast<double(*)[9][64]>(&xs[0][0][0] + (threadIdx.x >> 6) * (4 * 9 * 64));
+    const int lane = (int)(threadIdx.x & 63);
+    const bool near_x = t.x <= 8 || t.y >= K.nx - 8;
+    const bool near_y = WY && (t.z <= 8 || t.w >= K.ny - 8);
+    if (near_x && near_y)
+        fused_march<64, true, WY, PLK, PF, UNI, FF>(K, fin, fout, gyp, t.x, t.y, t.z, t.w, xw, lane);
+    else if (near_x)
+        fused_march<64, true, false, PLK, PF, UNI, FF>(K, fin, fout, gyp, t.x, t.y, t.z, t.w, xw, lane);
+    else if (near_y)
+        fused_march<64, false, WY, PLK, PF, UNI, FF>(K, fin, fout, gyp, t.x, t.y, t.z, t.w, xw, lane);
+    else
+        fused_march<64, false, false, PLK, PF, UNI, FF>(K, fin, fout, gyp, t.x, t.y, t.z, t.w, xw, lane);
+}
+
 template <int TW, bool WX, bool WY, int PLK, int PF, bool UNI, bool FF>
 __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __restrict__ fin, double* __restrict__ fout,
                                               const double* __restrict__ gyp, FusedGrid G)
@@ -495,6 +522,13 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
     int strip, ys0, ys1;
     if (G.table) {
         const int4 d = G.table[L];
+        if constexpr (WX && TW > 64) {
+            if (d.x < 0) {   // TW/64 independent single-wave tasks next to the x walls
+                wall_tasks<TW, WY, PLK, PF, UNI, FF>(K, fin, fout, gyp, G.table[G.nwg + (TW / 64) * (-1 - d.x) +
+                                                                                  (int)(threadIdx.x >> 6)], xs);
+                return;
+            }
+        }
         strip = d.x;
         ys0 = d.y;
         ys1 = d.z;
@@ -505,8 +539,8 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
         ys0 = (int)((unsigned)(seg * K.ny) / (unsigned)G.nsegs);
         ys1 = (int)((unsigned)((seg + 1) * K.ny) / (unsigned)G.nsegs);
     }
-    const int xs0 = (int)((unsigned)(strip * K.nx) / (unsigned)G.nstrips);
-    const int xs1 = (int)((unsigned)((strip + 1) * K.nx) / (unsigned)G.nstrips);
+    const int xs0 = G.xoff + (int)((unsigned)(strip * G.xspan) / (unsigned)G.nstrips);
+    const int xs1 = G.xoff + (int)((unsigned)((strip + 1) * G.xspan) / (unsigned)G.nstrips);
 
     if constexpr (WX || WY) {
         // A segment whose march (columns xs0-4..xs1+3, rows ys0-4..ys1+3) stays
@@ -518,21 +552,21 @@ __global__ __launch_bounds__(TW) void k_fused(StepConsts K, const double* __rest
         const bool near_x = WX && (xs0 <= 8 || xs1 >= K.nx - 8);
         const bool near_y = WY && (ys0 <= 8 || ys1 >= K.ny - 8);
         if (!near_x && !near_y) {
-            fused_march<TW, false, false, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
+            fused_march<TW, false, false, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs, (int)threadIdx.x);
             return;
         }
         if constexpr (WX && WY) {
             if (!near_y) {
-                fused_march<TW, true, false, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
+                fused_march<TW, true, false, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs, (int)threadIdx.x);
                 return;
             }
             if (!near_x) {
-                fused_march<TW, false, true, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
+                fused_march<TW, false, true, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs, (int)threadIdx.x);
                 return;
             }
         }
     }
-    fused_march<TW, WX, WY, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs);
+    fused_march<TW, WX, WY, PLK, PF, UNI, FF>(K, fin, fout, gyp, xs0, xs1, ys0, ys1, xs, (int)threadIdx.x);
 }
 
 // Batched step: table entry L = (strip, ys0, ys1, instance); every instance
@@ -552,7 +586,7 @@ __global__ __launch_bounds__(TW) void k_fused_batch(const BatchInst* __restrict_
     const int xs0 = (int)((unsigned)(d.x * I.K.nx) / (unsigned)nstrips);
     const int xs1 = (int)((unsigned)((d.x + 1) * I.K.nx) / (unsigned)nstrips);
     fused_march<TW, false, false, PLK, PF, true, false>(I.K, fin + I.off, fout + I.off, nullptr, xs0, xs1, d.y, d.z,
-                                                          xs);
+                                                          xs, (int)threadIdx.x);
 }
 
 

@@ -32,7 +32,8 @@ struct FusedShape {
     int seg_h;           // rows per segment, or <= 0 for the table
     int prefetch;        // rows loaded ahead of the one being collided (2 or 3)
     const int4* table;   // device segment table (used when seg_h <= 0)
-    int nwg;             // entries of the table
+    int nwg;             // workgroup entries of the table
+    int wall_tasks;      // 1: the table runs the columns next to the x walls as single-wave tasks
 };
 
 // Partition of the strips into segments so that the costliest segment is as
@@ -51,6 +52,18 @@ struct PlanGrid {
 };
 int balanced_partition_multi(const PlanGrid* grids, int count, int tile_w, int slots, double cx, double cy, int4* out,
                              int cap);
+
+// Columns next to each x wall that run as single-wave tasks (one 64-lane strip).
+constexpr int kWallCols = 56;
+
+// Wide strips (tile_w > 64) on a grid with x walls run the kWallCols columns
+// next to each x wall as single-wave tasks, tile_w/64 to a workgroup, and cut
+// only the columns between them into strips (see fusedk::FusedGrid).
+bool wall_tasks_apply(int nx, bool wall_x, int tile_w);
+// That plan: returns the number of workgroup entries (0 if it does not fit),
+// the whole table (entries and tasks) holding *total int4.
+int balanced_partition_wall_tasks(int nx, int ny, bool wall_y, int tile_w, int slots, double cx, double cy, int4* out,
+                                  int cap, int* total);
 
 // One instance of a batch, as the batched step kernels read it.
 struct BatchInst {

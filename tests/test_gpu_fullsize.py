@@ -175,3 +175,26 @@ def test_powerlaw_256_from_rest_500_steps(gpu, pl_n, shape):
     assert np.all(np.isfinite(f))
     # where the lid corners hold |f| above 1 (n = 1.5) the bar is relative
     assert np.all(d <= TOL * np.maximum(1.0, np.abs(fo)))
+
+
+@pytest.mark.parametrize("n", [127, 128, 183])
+@pytest.mark.parametrize("tw", [128, 256])
+def test_wall_tasks_at_their_threshold(gpu, n, tw):
+    """Walled grids just below, at and above the width (2 x 56 + 16 columns) from
+    which 128- and 256-lane kernels run the 56 columns next to each x wall as
+    single-wave tasks, against the oracle; at 128 columns the interior is one
+    strip of 16 and task groups hold empty tasks."""
+    from oracle.orc import Oracle
+    prob = P.cavity(n, re=400.0, lid=0.1)
+    prob.u0, prob.v0 = _wall_field(n, 21, 0.03)
+    s = gpu(prob, device="cuda:0")
+    s.set_kernel(1, tw, 0, 2)
+    say(f"[gpu parity] wall tasks: cavity {n}^2, {tw} lanes, 60 steps")
+    s.step(60)
+    f = s.save().cpu().numpy()
+    s.close()
+    o = Oracle(prob, threads=THREADS)
+    o.step(60)
+    err = np.abs(f - o.f()).max()
+    say(f"    max|df|={err:.3e}")
+    assert np.all(np.isfinite(f)) and err <= TOL
