@@ -488,7 +488,7 @@ __device__ __forceinline__ void fused_march(const StepConsts& K, const double* _
 }
 
 // One single-wave task (xs0, xs1, ys0, ys1) of a workgroup of TW lanes: a 64-lane march on
-// this wave's quarter of the workgroup's exchange buffers, with wave barriers only, so the
+// this wave's share of the workgroup's exchange buffers, with wave barriers only, so the
 // wave runs at its own pace.  An empty task (xs0 >= xs1) returns at once.
 template <int TW, bool WY, int PLK, int PF, bool UNI, bool FF>
 __device__ __forceinline__ void wall_tasks(const StepConsts& K, const double* __restrict__ fin,
